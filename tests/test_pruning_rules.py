@@ -1,0 +1,123 @@
+"""CPU proofs of the exact shortcuts the GPU decoder takes, before any GPU runs them.
+
+1. Rate-0 node (every leaf frozen): its partial sums are the frozen values
+   re-encoded, beta = v G_m, with no LLR work.
+2. Rate-1 node (no leaf frozen), FP32 min-sum: the partial sums depend only on
+   the sign / zero state of the node's input LLRs.  Hard decisions are NOT SC
+   when exact zeros occur (alpha = (0, -1) gives x-hat = (1, 1)), so the rule
+   is the three-state recursion, written here on 64-bit words exactly as the
+   kernel evaluates it:
+       left:  S_L = S_lo ^ S_hi,  Z_L = Z_lo | Z_hi
+       right: Z_R = Z_lo & Z_hi,  S_R = Z_hi ? (S_lo ^ beta_L) : S_hi
+       beta = [beta_L ^ beta_R, beta_R];  leaf: beta = S & ~Z
+   with the early exit "no zeros -> beta = S".
+3. The in-word polar transform x ^= (x >> h) & LOW_h for h = 1..32.
+Each is checked against the plain oracle (no shortcuts)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+
+M64 = (1 << 64) - 1
+LOW = {1: 0x5555555555555555, 2: 0x3333333333333333, 4: 0x0F0F0F0F0F0F0F0F,
+       8: 0x00FF00FF00FF00FF, 16: 0x0000FFFF0000FFFF, 32: 0x00000000FFFFFFFF}
+
+
+def nodemask(o, m):
+    return (((1 << m) - 1) << o) & M64
+
+
+def word_transform(x, m):
+    for h in (1, 2, 4, 8, 16, 32):
+        if h >= m:
+            break
+        x ^= (x >> h) & LOW[h]
+    return x
+
+
+def rate1_beta(S, Z, o, m):
+    nm = nodemask(o, m)
+    if Z & nm == 0:
+        return S & nm
+    if m == 1:
+        return S & ~Z & nm
+    h = m // 2
+    lo = nodemask(o, h)
+    SL = (S ^ (S >> h)) & lo
+    ZL = (Z | (Z >> h)) & lo
+    bL = rate1_beta(SL, ZL, o, h)
+    Zhi = Z >> h
+    Shi = S >> h
+    ZR = (Z & Zhi) & lo
+    SR = ((Zhi & (S ^ bL)) | (~Zhi & Shi)) & lo
+    bR = rate1_beta((SR << h) & M64, (ZR << h) & M64, o + h, h)
+    return (bL ^ (bR >> h)) | bR
+
+
+def _to_word(bits, o=0):
+    w = 0
+    for i, b in enumerate(bits):
+        w |= int(b) << (o + i)
+    return w
+
+
+def _sign_zero(llr, o=0):
+    S = _to_word([v < 0 for v in llr], o)
+    Z = _to_word([v == 0 for v in llr], o)
+    return S, Z
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 8])
+def test_rate1_three_state_exhaustive(m):
+    g = np.random.default_rng(m)
+    for pattern in itertools.product((-1, 0, 1), repeat=m):
+        mag = (0.5 + g.random(m)).astype(np.float32)
+        llr = (np.array(pattern, np.float32) * mag).astype(np.float32)
+        _, _, beta = oracle.sc_decode(llr, np.zeros(m, np.uint8), np.zeros(m, np.uint8), want_beta=True)
+        for o in (0, 64 - m):
+            S, Z = _sign_zero(llr, o)
+            assert rate1_beta(S, Z, o, m) == _to_word(beta, o), (pattern, o)
+
+
+@pytest.mark.parametrize("m", [16, 32, 64])
+def test_rate1_three_state_random(m):
+    g = np.random.default_rng(100 + m)
+    for trial in range(400):
+        pz = [0.0, 0.05, 0.3, 0.7][trial % 4]
+        llr = (g.integers(-3, 4, m) * (1 + g.random(m))).astype(np.float32)
+        llr[g.random(m) < pz] = 0.0
+        _, _, beta = oracle.sc_decode(llr, np.zeros(m, np.uint8), np.zeros(m, np.uint8), want_beta=True)
+        o = 0 if m == 64 else int(g.integers(0, 64 // m)) * m
+        S, Z = _sign_zero(llr, o)
+        assert rate1_beta(S, Z, o, m) == _to_word(beta, o)
+
+
+def test_rate1_no_zero_is_hard_decision():
+    g = np.random.default_rng(5)
+    for _ in range(200):
+        llr = (g.standard_normal(64)).astype(np.float32)
+        llr[llr == 0] = 1.0
+        _, _, beta = oracle.sc_decode(llr, np.zeros(64, np.uint8), np.zeros(64, np.uint8), want_beta=True)
+        assert np.array_equal(beta, (llr < 0).astype(np.uint8))
+
+
+def test_rate0_beta_is_reencoded_frozen_values():
+    g = np.random.default_rng(6)
+    for m in (1, 2, 4, 8, 16, 32, 64):
+        for _ in range(20):
+            v = g.integers(0, 2, m).astype(np.uint8)
+            llr = g.standard_normal(m).astype(np.float32)
+            u, _, beta = oracle.sc_decode(llr, np.ones(m, np.uint8), v, want_beta=True)
+            assert np.array_equal(u, v)
+            assert word_transform(_to_word(v), m) == _to_word(beta)
+
+
+def test_word_transform_is_the_encoder():
+    g = np.random.default_rng(7)
+    for m in (1, 2, 4, 8, 16, 32, 64):
+        for _ in range(20):
+            u = g.integers(0, 2, m).astype(np.uint8)
+            x = oracle.encode(m.bit_length() - 1, u)
+            assert word_transform(_to_word(u), m) == _to_word(x)
