@@ -1,0 +1,175 @@
+/*
+ * libpolar: successive-cancellation (SC) decoding of long polar codes on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The decoding problem is the one of Section 1 and Section 3 of Jouguet and
+ * Kunz-Jacques, "High performance error correction for quantum key
+ * distribution using polar codes": Alice's string is the polar codeword
+ * (no encoding step), the values of the frozen bits of u = x G_N are
+ * revealed over the classical channel, and Bob recovers u-hat from the LLRs
+ * of his own string with the recursive SC decoder of Section 4.
+ *
+ * Conventions for every call:
+ *   - Return value: POLAR_OK (0) or a negative POLAR_E_* code; the message of
+ *     the last failing call on this thread is available from
+ *     polar_last_error().  Nothing aborts the process.
+ *   - Bit vectors are packed little-endian into uint32 words: bit i of a
+ *     length-N vector is bit (i & 31) of word (i >> 5).  A vector of N < 32
+ *     bits occupies one word whose unused high bits are zero on output and
+ *     ignored on input.
+ *   - LLRs are float32, L = ln P(bit = 0 | y) / P(bit = 1 | y).
+ *   - Pointers documented as "device" must point to memory of the device the
+ *     context (or the call) runs on; "host" pointers to host memory.  The
+ *     caller owns every buffer; the library frees nothing it did not
+ *     allocate.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued asynchronously; outputs are valid once the
+ *     stream has been synchronised.  Argument errors are reported
+ *     synchronously with nothing enqueued; errors raised by the device show
+ *     up as POLAR_E_DEVICE from a later call.
+ */
+#ifndef POLAR_H
+#define POLAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define POLAR_OK 0
+#define POLAR_E_INVAL (-1)     /* bad argument (size, pointer, option)            */
+#define POLAR_E_NOMEM (-2)     /* workspace / arena too small                     */
+#define POLAR_E_DEVICE (-3)    /* HIP runtime or device error                     */
+#define POLAR_E_BUSY (-4)      /* serving queue full                              */
+#define POLAR_E_CANCELLED (-5) /* serving request cancelled before it ran         */
+
+/* Check-node update used by SC decoding (Section 4). */
+#define POLAR_F_MINSUM 0  /* sign(a) sign(b) min(|a|,|b|), FP32, bit-exact        */
+#define POLAR_F_BOXPLUS 1 /* 2 atanh(tanh(a/2) tanh(b/2)) (the phi-function form), FP32 */
+
+#define POLAR_MAX_LOG2N 24
+
+/* Message describing the last failing call made by this thread ("" if none). */
+const char* polar_last_error(void);
+
+/* Library version string. */
+const char* polar_version(void);
+
+/*
+ * Frozen set from the Bhattacharyya parameters of the synthetic channels
+ * (Section 3: the lowest-capacity bits are frozen; the frozen set can be
+ * chosen so that the bound on the frame error rate is 0.1).  Host only.
+ *
+ * One polarisation step maps Z to 2Z - Z^2 for the first-decoded ("minus")
+ * channel and to Z^2 for the other; index i applies the step selected by its
+ * most significant bit first.  Z is carried as (ln Z, ln(1 - Z)) in double so
+ * that it does not saturate at 1.  Channels are ranked by
+ * r_i = ln((1 - Z_i) / Z_i); the least reliable are frozen, exact ties
+ * freezing the lower index first.
+ *
+ *   log2n        1 .. POLAR_MAX_LOG2N
+ *   z0           Bhattacharyya parameter of the channel, 0 < z0 < 1
+ *                (BSC(p): 2 sqrt(p(1-p)); BPSK/AWGN(sigma): exp(-1/(2 sigma^2)))
+ *   n_frozen     >= 0: freeze exactly this many (<= N);
+ *                -1: union-bound rule, the largest information set whose
+ *                sum of Z_i is <= fer_bound
+ *   fer_bound    used only when n_frozen == -1 (e.g. 0.1)
+ *   frozen_mask  host out, max(1, N/32) words, 1 = frozen
+ *   r_out        host out, N doubles, or NULL
+ *   n_frozen_out host out, or NULL
+ */
+int polar_build_frozen_set(int log2n, double z0, int64_t n_frozen, double fer_bound,
+                           uint32_t* frozen_mask, double* r_out, int64_t* n_frozen_out);
+
+/*
+ * x = u G_N over GF(2) with G_N the n-fold Kronecker power of [[1,0],[1,1]],
+ * natural index order (Arikan's construction, cited in Section 3).  Used to
+ * re-encode u-hat (x-hat = u-hat G_N) and to build test frames; G_N G_N = I,
+ * so the same call also inverts it.
+ *
+ *   log2n     0 .. POLAR_MAX_LOG2N
+ *   n_frames  >= 0; frame k uses words [k W, (k+1) W), W = max(1, N/32)
+ *   u, x      device, n_frames * W words each; x may equal u (in place)
+ */
+int polar_encode(int log2n, int n_frames, const uint32_t* u, uint32_t* x, void* stream);
+
+/* One frame to decode.  All pointers are device pointers. */
+typedef struct polar_frame {
+    int32_t log2n;                /* 1 .. POLAR_MAX_LOG2N                              */
+    int32_t f_kind;               /* POLAR_F_MINSUM or POLAR_F_BOXPLUS                  */
+    const float* llr;             /* N channel LLRs                                      */
+    const uint32_t* frozen_mask;  /* max(1, N/32) words, 1 = frozen; may be shared      */
+    const uint32_t* frozen_vals;  /* max(1, N/32) words, revealed values of u_F;
+                                     bits outside the mask are ignored                 */
+    uint32_t* u_hat;              /* out, max(1, N/32) words; frozen positions hold
+                                     frozen_vals                                       */
+    float* leaf_llr;              /* out, N floats (decision LLR of every leaf), or
+                                     NULL.  Leaves inside nodes skipped by pruning
+                                     are left unwritten.                              */
+} polar_frame;
+
+typedef struct polar_ctx polar_ctx;
+
+/* Options for polar_ctx_set_option. */
+#define POLAR_OPT_PRUNE 1       /* 0/1: exact rate-0 / rate-1 node shortcuts (default 1) */
+#define POLAR_OPT_CUTOVER 2     /* log2 of the register-resident subtree, 6..12;
+                                   0 = automatic (default)                               */
+#define POLAR_OPT_WG_WAVES 3    /* wavefronts per workgroup: 1, 2, 4, 8 or 16; 0 = auto */
+#define POLAR_OPT_MAX_SLOTS 4   /* max frames in flight (workgroups); 0 = auto          */
+
+/*
+ * Create a decoding context on a device.  The context owns only host-side
+ * state (options, a pinned staging buffer for frame descriptors); device
+ * scratch is the caller's workspace, attached with polar_ctx_set_workspace.
+ *   device     HIP device ordinal
+ *   workspace  device pointer or NULL (attach later)
+ *   ws_bytes   size of workspace in bytes
+ */
+int polar_ctx_create(polar_ctx** out, int device, void* workspace, size_t ws_bytes);
+int polar_ctx_destroy(polar_ctx* ctx);
+int polar_ctx_set_workspace(polar_ctx* ctx, void* workspace, size_t ws_bytes);
+int polar_ctx_set_option(polar_ctx* ctx, int option, int64_t value);
+int polar_ctx_get_option(polar_ctx* ctx, int option, int64_t* value);
+
+/*
+ * Workspace bytes polar_sc_decode_batch needs for these frames under the
+ * context's current options (host array of n_frames descriptors; only log2n
+ * and f_kind are read).  Roughly 4N + N/8 bytes per frame in flight.
+ * Returns 0 on invalid arguments.
+ */
+size_t polar_workspace_bytes(const polar_ctx* ctx, const polar_frame* frames, int n_frames);
+
+/*
+ * Decode a batch of frames (Section 4's SC rule; Section 4 also notes that SC
+ * admits only "external" parallelism across frames, which is how the batch is
+ * spread over the GPU).  Frames may differ in N, rate, mask and f_kind.  One
+ * persistent launch per f_kind: workgroups take frames from a device queue,
+ * longest first.  Results depend only on the frame, not on the batch.
+ *   frames    host array of n_frames descriptors (copied before return)
+ *   n_frames  >= 0
+ * Errors: POLAR_E_INVAL (descriptor), POLAR_E_NOMEM (workspace too small),
+ * POLAR_E_DEVICE.
+ */
+int polar_sc_decode_batch(polar_ctx* ctx, const polar_frame* frames, int n_frames, void* stream);
+
+/*
+ * Plain per-frame GPU decoder, kept as the baseline the batched decoder is
+ * measured against: one launch per frame, one workgroup, no pruning, frames
+ * serially on the stream.  Same arguments, workspace and results.
+ */
+int polar_sc_decode_plain(polar_ctx* ctx, const polar_frame* frames, int n_frames, void* stream);
+
+/*
+ * Diagnostics: exercises the cross-lane moves (DPP row shifts, permlane
+ * swaps), the bit-matrix transpose and the cross-lane polar transform the
+ * decoder is built from.  out: device, 1024 words.
+ */
+int polar_debug_lane_selftest(uint32_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLAR_H */

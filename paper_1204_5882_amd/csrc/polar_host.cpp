@@ -1,0 +1,424 @@
+// libpolar C ABI: argument validation, the host-side frozen-set builder,
+// context / workspace management and kernel launches.  Device code lives in
+// sc_device.hip.
+#include "polar.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sc_device.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() { return POLAR_OK; }
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(POLAR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Keeps the caller's current device unchanged across a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int64_t words_of(int log2n) { return log2n >= 5 ? ((int64_t)1 << (log2n - 5)) : 1; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Frozen set (Section 3): Bhattacharyya parameters of the synthetic channels,
+// carried as (ln Z, ln(1 - Z)) so that Z does not saturate at 1 in double.
+// ---------------------------------------------------------------------------
+namespace {
+
+// ln(1 - e^x) for x < 0 (Maechler's two-branch evaluation).
+double ln_one_minus_exp(double x) { return x > -M_LN2 ? std::log(-std::expm1(x)) : std::log1p(-std::exp(x)); }
+
+// In-place expansion: after step t, entries [0, 2^t) hold the channels of a
+// length-2^t code; entry j spawns 2j (first-decoded, Z' = 2Z - Z^2) and
+// 2j + 1 (Z' = Z^2).  Walking j downwards keeps the parents intact.
+void bhattacharyya_pairs(int log2n, double z0, std::vector<double>& lz, std::vector<double>& lw) {
+    const int64_t n = (int64_t)1 << log2n;
+    lz.assign((size_t)n, 0.0);
+    lw.assign((size_t)n, 0.0);
+    lz[0] = std::log(z0);
+    lw[0] = std::log1p(-z0);
+    for (int t = 0; t < log2n; ++t) {
+        const int64_t cnt = (int64_t)1 << t;
+        for (int64_t j = cnt - 1; j >= 0; --j) {
+            const double a = lz[(size_t)j], b = lw[(size_t)j];
+            const bool z_small = std::exp(a) < 0.5;
+            // 1 - Z^- = (1 - Z)^2 ;  Z^- = Z (2 - Z) = Z (1 + (1 - Z))
+            const double wm = 2.0 * b;
+            const double zm = z_small ? a + std::log1p(std::exp(b)) : ln_one_minus_exp(wm);
+            // Z^+ = Z^2 ;  1 - Z^+ = (1 - Z)(1 + Z)
+            const double zp = 2.0 * a;
+            const double wp = std::exp(a) > 0.5 ? b + std::log1p(std::exp(a)) : ln_one_minus_exp(zp);
+            lz[(size_t)(2 * j)] = zm;
+            lw[(size_t)(2 * j)] = wm;
+            lz[(size_t)(2 * j + 1)] = zp;
+            lw[(size_t)(2 * j + 1)] = wp;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" const char* polar_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* polar_version(void) { return "libpolar 0.1 (gfx950)"; }
+
+extern "C" int polar_build_frozen_set(int log2n, double z0, int64_t n_frozen, double fer_bound,
+                                      uint32_t* frozen_mask, double* r_out, int64_t* n_frozen_out) {
+    if (log2n < 1 || log2n > POLAR_MAX_LOG2N) return fail(POLAR_E_INVAL, "log2n %d outside 1..%d", log2n, POLAR_MAX_LOG2N);
+    if (!(z0 > 0.0 && z0 < 1.0)) return fail(POLAR_E_INVAL, "z0 must lie in (0, 1)");
+    if (!frozen_mask) return fail(POLAR_E_INVAL, "frozen_mask is NULL");
+    const int64_t n = (int64_t)1 << log2n;
+    if (n_frozen > n || n_frozen < -1) return fail(POLAR_E_INVAL, "n_frozen %lld outside -1..N", (long long)n_frozen);
+    if (n_frozen == -1 && !(fer_bound >= 0.0)) return fail(POLAR_E_INVAL, "fer_bound must be >= 0");
+
+    std::vector<double> lz, lw;
+    bhattacharyya_pairs(log2n, z0, lz, lw);
+    std::vector<double> r((size_t)n);
+    for (int64_t i = 0; i < n; ++i) r[(size_t)i] = lw[(size_t)i] - lz[(size_t)i];
+    if (r_out) std::memcpy(r_out, r.data(), sizeof(double) * (size_t)n);
+
+    // total order: ascending reliability, ties by index
+    std::vector<int64_t> idx((size_t)n);
+    std::iota(idx.begin(), idx.end(), 0);
+    auto less = [&](int64_t a, int64_t b) { return r[(size_t)a] < r[(size_t)b] || (r[(size_t)a] == r[(size_t)b] && a < b); };
+    int64_t nf = n_frozen;
+    if (nf == -1) {
+        std::sort(idx.begin(), idx.end(), less);
+        double sum = 0.0;
+        int64_t k = 0;
+        for (; k < n; ++k) {
+            const double z = std::exp(lz[(size_t)idx[(size_t)(n - 1 - k)]]);
+            if (sum + z > fer_bound) break;
+            sum += z;
+        }
+        nf = n - k;
+    } else if (nf > 0 && nf < n) {
+        std::nth_element(idx.begin(), idx.begin() + nf, idx.end(), less);
+    }
+    const int64_t nw = words_of(log2n);
+    std::memset(frozen_mask, 0, sizeof(uint32_t) * (size_t)nw);
+    for (int64_t t = 0; t < nf; ++t) {
+        const int64_t i = idx[(size_t)t];
+        frozen_mask[i >> 5] |= 1u << (i & 31);
+    }
+    if (n_frozen_out) *n_frozen_out = nf;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Encoder.
+// ---------------------------------------------------------------------------
+extern "C" int polar_encode(int log2n, int n_frames, const uint32_t* u, uint32_t* x, void* stream) {
+    if (log2n < 0 || log2n > POLAR_MAX_LOG2N) return fail(POLAR_E_INVAL, "log2n %d outside 0..%d", log2n, POLAR_MAX_LOG2N);
+    if (n_frames < 0) return fail(POLAR_E_INVAL, "n_frames < 0");
+    if (n_frames == 0) return ok();
+    if (!u || !x) return fail(POLAR_E_INVAL, "NULL buffer");
+    hipError_t e = polar_dev_encode(log2n, n_frames, u, x, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "encode launch");
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Context.
+// ---------------------------------------------------------------------------
+struct polar_ctx {
+    int device = 0;
+    int n_cu = 256;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int prune = 1;
+    int cutover = 0;    // 0 = automatic
+    int waves = 0;      // 0 = automatic
+    int max_slots = 0;  // 0 = automatic
+    FrameDesc* staging = nullptr;  // pinned host copy of the descriptor table
+    size_t staging_cap = 0;
+    hipEvent_t staged = nullptr;   // recorded after the last descriptor upload
+    bool staged_pending = false;
+};
+
+namespace {
+
+int eff_cutover(const polar_ctx* c) { return c->cutover ? c->cutover : 12; }
+int eff_waves(const polar_ctx* c) { return c->waves ? c->waves : 4; }
+int eff_max_slots(const polar_ctx* c) { return c->max_slots ? c->max_slots : 2 * c->n_cu; }
+
+constexpr size_t kHeaderBytes = 256;  // work counters
+
+struct Plan {
+    std::vector<FrameDesc> descs;  // sorted, grouped
+    struct Group { int fk, dump, first, count; };
+    std::vector<Group> groups;
+    int slots = 0;
+    int64_t slot_bytes = 0;
+    size_t desc_off = 0, slot_off = 0, total = 0;
+};
+
+int validate_frames(const polar_frame* frames, int n_frames) {
+    if (n_frames < 0) return fail(POLAR_E_INVAL, "n_frames < 0");
+    if (n_frames > 0 && !frames) return fail(POLAR_E_INVAL, "frames is NULL");
+    for (int i = 0; i < n_frames; ++i) {
+        const polar_frame& f = frames[i];
+        if (f.log2n < 1 || f.log2n > POLAR_MAX_LOG2N)
+            return fail(POLAR_E_INVAL, "frame %d: log2n %d outside 1..%d", i, f.log2n, POLAR_MAX_LOG2N);
+        if (f.f_kind != POLAR_F_MINSUM && f.f_kind != POLAR_F_BOXPLUS)
+            return fail(POLAR_E_INVAL, "frame %d: unknown f_kind %d", i, f.f_kind);
+        if (!f.llr || !f.frozen_mask || !f.frozen_vals || !f.u_hat)
+            return fail(POLAR_E_INVAL, "frame %d: NULL buffer", i);
+        if (((uintptr_t)f.llr & 3) || ((uintptr_t)f.frozen_mask & 3) || ((uintptr_t)f.frozen_vals & 3) ||
+            ((uintptr_t)f.u_hat & 3) || ((uintptr_t)f.leaf_llr & 3))
+            return fail(POLAR_E_INVAL, "frame %d: buffers must be 4-byte aligned", i);
+    }
+    return ok();
+}
+
+// Layout of the workspace for a batch: [counters | descriptors | slots].
+void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool plain, Plan& p) {
+    const int cut = plain ? 12 : eff_cutover(c);
+    std::vector<int> order((size_t)n_frames);
+    std::iota(order.begin(), order.end(), 0);
+    // group by (f_kind, leaf dump); inside a group, most work first
+    auto key = [&](int i) { return frames[i].f_kind * 2 + (frames[i].leaf_llr ? 1 : 0); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (key(a) != key(b)) return key(a) < key(b);
+        return frames[a].log2n > frames[b].log2n;
+    });
+    p.descs.clear();
+    p.groups.clear();
+    int maxlog = 0;
+    for (int k = 0; k < n_frames; ++k) {
+        const polar_frame& f = frames[order[(size_t)k]];
+        FrameDesc d{};
+        d.llr = f.llr;
+        d.mask = f.frozen_mask;
+        d.vals = f.frozen_vals;
+        d.uhat = f.u_hat;
+        d.leaf = f.leaf_llr;
+        d.log2n = f.log2n;
+        d.fkind = f.f_kind;
+        p.descs.push_back(d);
+        maxlog = std::max(maxlog, (int)f.log2n);
+        if (p.groups.empty() || key(order[(size_t)k]) != p.groups.back().fk * 2 + p.groups.back().dump)
+            p.groups.push_back({f.f_kind, f.leaf_llr ? 1 : 0, k, 0});
+        p.groups.back().count++;
+    }
+    int slots = 0;
+    for (auto& g : p.groups) slots = std::max(slots, plain ? 1 : std::min(g.count, eff_max_slots(c)));
+    p.slots = slots;
+    p.slot_bytes = n_frames ? polar_dev_slot_bytes(maxlog, cut) : 0;
+    p.desc_off = kHeaderBytes;
+    p.slot_off = align256(p.desc_off + sizeof(FrameDesc) * (size_t)n_frames);
+    p.total = p.slot_off + (size_t)p.slots * (size_t)p.slot_bytes;
+}
+
+int upload_descs(polar_ctx* c, const Plan& p, hipStream_t s) {
+    const size_t n = p.descs.size();
+    if (n == 0) return ok();
+    if (c->staged_pending) {
+        hipError_t e = hipEventSynchronize(c->staged);
+        if (e != hipSuccess) return hip_fail(e, "descriptor staging");
+        c->staged_pending = false;
+    }
+    if (n > c->staging_cap) {
+        if (c->staging) (void)hipHostFree(c->staging);
+        c->staging = nullptr;
+        size_t cap = std::max(n, (size_t)1024);
+        hipError_t e = hipHostMalloc((void**)&c->staging, cap * sizeof(FrameDesc), hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "pinned descriptor buffer");
+        c->staging_cap = cap;
+    }
+    std::memcpy(c->staging, p.descs.data(), n * sizeof(FrameDesc));
+    hipError_t e = hipMemcpyAsync((uint8_t*)c->ws + p.desc_off, c->staging, n * sizeof(FrameDesc),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    e = hipEventRecord(c->staged, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload event");
+    c->staged_pending = true;
+    return ok();
+}
+
+int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* stream, bool plain) {
+    if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
+    int rc = validate_frames(frames, n_frames);
+    if (rc) return rc;
+    if (n_frames == 0) return ok();
+    Plan p;
+    make_plan(c, frames, n_frames, plain, p);
+    if (!c->ws || c->ws_bytes < p.total)
+        return fail(POLAR_E_NOMEM, "workspace of %zu bytes < %zu required", c->ws_bytes, p.total);
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(POLAR_E_DEVICE, "cannot select device %d", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    rc = upload_descs(c, p, s);
+    if (rc) return rc;
+    uint8_t* base = (uint8_t*)c->ws;
+    unsigned* counter = (unsigned*)base;
+    const FrameDesc* dtab = (const FrameDesc*)(base + p.desc_off);
+    uint8_t* slots = base + p.slot_off;
+    const int cut = plain ? 12 : eff_cutover(c);
+    const int waves = plain ? 4 : eff_waves(c);
+    const int prune = plain ? 0 : c->prune;
+    for (const auto& gr : p.groups) {
+        if (plain) {
+            for (int k = 0; k < gr.count; ++k) {
+                hipError_t e = polar_dev_launch_decode(cut, gr.fk, prune, gr.dump, waves, dtab + gr.first + k, 1,
+                                                       counter, slots, p.slot_bytes, 1, s);
+                if (e != hipSuccess) return hip_fail(e, "decode launch");
+            }
+        } else {
+            const int grid = std::min(gr.count, eff_max_slots(c));
+            hipError_t e = polar_dev_launch_decode(cut, gr.fk, prune, gr.dump, waves, dtab + gr.first, gr.count,
+                                                   counter, slots, p.slot_bytes, grid, s);
+            if (e != hipSuccess) return hip_fail(e, "decode launch");
+        }
+    }
+    return ok();
+}
+
+}  // namespace
+
+extern "C" int polar_ctx_create(polar_ctx** out, int device, void* workspace, size_t ws_bytes) {
+    if (!out) return fail(POLAR_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(POLAR_E_INVAL, "device %d outside 0..%d", device, ndev - 1);
+    DeviceGuard g(device);
+    if (!g.ok) return fail(POLAR_E_DEVICE, "cannot select device %d", device);
+    polar_ctx* c = new polar_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipEventCreate");
+    }
+    c->ws = workspace;
+    c->ws_bytes = workspace ? ws_bytes : 0;
+    *out = c;
+    return ok();
+}
+
+extern "C" int polar_ctx_destroy(polar_ctx* c) {
+    if (!c) return ok();
+    {
+        DeviceGuard g(c->device);
+        if (c->staged) {
+            (void)hipEventSynchronize(c->staged);
+            (void)hipEventDestroy(c->staged);
+        }
+        if (c->staging) (void)hipHostFree(c->staging);
+    }
+    delete c;
+    return ok();
+}
+
+extern "C" int polar_ctx_set_workspace(polar_ctx* c, void* workspace, size_t ws_bytes) {
+    if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(POLAR_E_INVAL, "workspace must be 256-byte aligned");
+    c->ws = workspace;
+    c->ws_bytes = workspace ? ws_bytes : 0;
+    return ok();
+}
+
+extern "C" int polar_ctx_set_option(polar_ctx* c, int option, int64_t value) {
+    if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
+    switch (option) {
+        case POLAR_OPT_PRUNE:
+            if (value != 0 && value != 1) return fail(POLAR_E_INVAL, "prune must be 0 or 1");
+            c->prune = (int)value;
+            return ok();
+        case POLAR_OPT_CUTOVER:
+            if (value != 0 && !polar_dev_cutover_supported((int)value))
+                return fail(POLAR_E_INVAL, "cutover %lld not built", (long long)value);
+            c->cutover = (int)value;
+            return ok();
+        case POLAR_OPT_WG_WAVES:
+            if (value != 0 && !polar_dev_waves_supported((int)value))
+                return fail(POLAR_E_INVAL, "waves per workgroup %lld not built", (long long)value);
+            c->waves = (int)value;
+            return ok();
+        case POLAR_OPT_MAX_SLOTS:
+            if (value < 0 || value > (1 << 20)) return fail(POLAR_E_INVAL, "max_slots out of range");
+            c->max_slots = (int)value;
+            return ok();
+        default:
+            return fail(POLAR_E_INVAL, "unknown option %d", option);
+    }
+}
+
+extern "C" int polar_ctx_get_option(polar_ctx* c, int option, int64_t* value) {
+    if (!c || !value) return fail(POLAR_E_INVAL, "NULL argument");
+    switch (option) {
+        case POLAR_OPT_PRUNE: *value = c->prune; return ok();
+        case POLAR_OPT_CUTOVER: *value = eff_cutover(c); return ok();
+        case POLAR_OPT_WG_WAVES: *value = eff_waves(c); return ok();
+        case POLAR_OPT_MAX_SLOTS: *value = eff_max_slots(c); return ok();
+        default: return fail(POLAR_E_INVAL, "unknown option %d", option);
+    }
+}
+
+extern "C" size_t polar_workspace_bytes(const polar_ctx* c, const polar_frame* frames, int n_frames) {
+    if (!c || n_frames < 0 || (n_frames > 0 && !frames)) return 0;
+    for (int i = 0; i < n_frames; ++i)
+        if (frames[i].log2n < 1 || frames[i].log2n > POLAR_MAX_LOG2N) return 0;
+    Plan p;
+    make_plan(c, frames, n_frames, false, p);
+    Plan q;
+    make_plan(c, frames, n_frames, true, q);
+    return std::max(p.total, q.total);
+}
+
+extern "C" int polar_sc_decode_batch(polar_ctx* c, const polar_frame* frames, int n_frames, void* stream) {
+    return decode_impl(c, frames, n_frames, stream, false);
+}
+
+extern "C" int polar_sc_decode_plain(polar_ctx* c, const polar_frame* frames, int n_frames, void* stream) {
+    return decode_impl(c, frames, n_frames, stream, true);
+}
+
+extern "C" int polar_debug_lane_selftest(uint32_t* out, void* stream) {
+    if (!out) return fail(POLAR_E_INVAL, "out is NULL");
+    hipError_t e = polar_dev_lane_selftest(out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "selftest launch");
+    return ok();
+}

@@ -1,0 +1,237 @@
+"""Thin Python binding of libpolar (include/polar.h) over ctypes.
+
+Argument marshalling only: every step of encoding and decoding runs in the
+library's HIP kernels.  PyTorch provides device memory and streams.  Bit
+vectors are torch.int32 tensors holding the packed uint32 words (bit i in
+word i >> 5 at position i & 31).
+
+If libpolar.so has not been built, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpolar.so")
+
+POLAR_OK = 0
+POLAR_E_INVAL = -1
+POLAR_E_NOMEM = -2
+POLAR_E_DEVICE = -3
+POLAR_E_BUSY = -4
+POLAR_E_CANCELLED = -5
+
+POLAR_F_MINSUM = 0
+POLAR_F_BOXPLUS = 1
+POLAR_MAX_LOG2N = 24
+
+POLAR_OPT_PRUNE = 1
+POLAR_OPT_CUTOVER = 2
+POLAR_OPT_WG_WAVES = 3
+POLAR_OPT_MAX_SLOTS = 4
+
+# every symbol declared in include/polar.h
+EXPORTED = [
+    "polar_last_error", "polar_version", "polar_build_frozen_set", "polar_encode",
+    "polar_ctx_create", "polar_ctx_destroy", "polar_ctx_set_workspace", "polar_ctx_set_option",
+    "polar_ctx_get_option", "polar_workspace_bytes", "polar_sc_decode_batch",
+    "polar_sc_decode_plain", "polar_debug_lane_selftest",
+]
+
+
+class PolarError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpolar error {code}: {msg}")
+        self.code = code
+
+
+class polar_frame(ctypes.Structure):
+    _fields_ = [
+        ("log2n", ctypes.c_int32),
+        ("f_kind", ctypes.c_int32),
+        ("llr", ctypes.c_void_p),
+        ("frozen_mask", ctypes.c_void_p),
+        ("frozen_vals", ctypes.c_void_p),
+        ("u_hat", ctypes.c_void_p),
+        ("leaf_llr", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libpolar.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python -m paper_1204_5882_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "polar_last_error": ([], ctypes.c_char_p),
+        "polar_version": ([], ctypes.c_char_p),
+        "polar_build_frozen_set": ([I, ctypes.c_double, I64, ctypes.c_double, P, P, P], I),
+        "polar_encode": ([I, I, P, P, P], I),
+        "polar_ctx_create": ([P, I, P, SZ], I),
+        "polar_ctx_destroy": ([P], I),
+        "polar_ctx_set_workspace": ([P, P, SZ], I),
+        "polar_ctx_set_option": ([P, I, I64], I),
+        "polar_ctx_get_option": ([P, I, P], I),
+        "polar_workspace_bytes": ([P, P, I], SZ),
+        "polar_sc_decode_batch": ([P, P, I, P], I),
+        "polar_sc_decode_plain": ([P, P, I, P], I),
+        "polar_debug_lane_selftest": ([P, P], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != POLAR_OK:
+        raise PolarError(rc, load().polar_last_error().decode())
+
+
+def last_error() -> str:
+    return load().polar_last_error().decode()
+
+
+def version() -> str:
+    return load().polar_version().decode()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def n_words(log2n: int) -> int:
+    return max(1, (1 << log2n) // 32)
+
+
+def build_frozen_set(log2n: int, z0: float, n_frozen: int = -1, fer_bound: float = 0.1,
+                     want_r: bool = False):
+    """Host-side Bhattacharyya frozen set.  Returns (mask words uint32, n_frozen, r or None)."""
+    mask = np.zeros(n_words(log2n), np.uint32)
+    r = np.empty(1 << log2n, np.float64) if want_r else None
+    nf = ctypes.c_int64(0)
+    _check(load().polar_build_frozen_set(int(log2n), float(z0), int(n_frozen), float(fer_bound),
+                                         mask.ctypes.data, None if r is None else r.ctypes.data,
+                                         ctypes.addressof(nf)))
+    return mask, int(nf.value), r
+
+
+def encode(log2n: int, u, x=None, n_frames: Optional[int] = None, stream=None):
+    """x = u G_N for packed frames (torch int32 tensors on the GPU); returns x."""
+    import torch
+
+    if x is None:
+        x = torch.empty_like(u)
+    w = n_words(log2n)
+    if n_frames is None:
+        n_frames = u.numel() // w
+    if u.numel() < n_frames * w or x.numel() < n_frames * w:
+        raise ValueError("buffers too small")
+    _check(load().polar_encode(int(log2n), int(n_frames), _ptr(u), _ptr(x), _stream_handle(stream)))
+    return x
+
+
+def lane_selftest(stream=None):
+    import torch
+
+    out = torch.zeros(1024, dtype=torch.int32, device="cuda")
+    _check(load().polar_debug_lane_selftest(_ptr(out), _stream_handle(stream)))
+    return out
+
+
+def make_frames(items: Sequence[dict]) -> ctypes.Array:
+    """items: dicts with log2n, f_kind, llr, frozen_mask, frozen_vals, u_hat,
+    optional leaf_llr (torch tensors on the device)."""
+    arr = (polar_frame * max(1, len(items)))()
+    for i, it in enumerate(items):
+        arr[i].log2n = int(it["log2n"])
+        arr[i].f_kind = int(it.get("f_kind", POLAR_F_MINSUM))
+        arr[i].llr = _ptr(it["llr"])
+        arr[i].frozen_mask = _ptr(it["frozen_mask"])
+        arr[i].frozen_vals = _ptr(it["frozen_vals"])
+        arr[i].u_hat = _ptr(it["u_hat"])
+        arr[i].leaf_llr = _ptr(it.get("leaf_llr"))
+    return arr
+
+
+class Ctx:
+    """A polar_ctx plus a workspace tensor it grows on demand."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        _check(self._lib.polar_ctx_create(ctypes.addressof(self._h), int(device), None, 0))
+        self.device = device
+        self.workspace = None
+
+    def close(self):
+        if self._h:
+            self._lib.polar_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, opt: int, value: int):
+        _check(self._lib.polar_ctx_set_option(self._h, int(opt), int(value)))
+
+    def get_option(self, opt: int) -> int:
+        v = ctypes.c_int64(0)
+        _check(self._lib.polar_ctx_get_option(self._h, int(opt), ctypes.addressof(v)))
+        return int(v.value)
+
+    def workspace_bytes(self, frames: ctypes.Array, n: int) -> int:
+        return int(self._lib.polar_workspace_bytes(self._h, frames, int(n)))
+
+    def set_workspace(self, tensor):
+        self.workspace = tensor
+        _check(self._lib.polar_ctx_set_workspace(self._h, _ptr(tensor),
+                                                 0 if tensor is None else tensor.numel() * tensor.element_size()))
+
+    def ensure_workspace(self, frames: ctypes.Array, n: int):
+        import torch
+
+        need = self.workspace_bytes(frames, n)
+        have = 0 if self.workspace is None else self.workspace.numel()
+        if need > have:
+            # torch's caching allocator returns 512-byte aligned blocks
+            self.set_workspace(torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}"))
+
+    def decode_batch(self, frames: ctypes.Array, n: int, stream=None):
+        _check(self._lib.polar_sc_decode_batch(self._h, frames, int(n), _stream_handle(stream)))
+
+    def decode_plain(self, frames: ctypes.Array, n: int, stream=None):
+        _check(self._lib.polar_sc_decode_plain(self._h, frames, int(n), _stream_handle(stream)))
+
+    def decode(self, items: Iterable[dict], plain: bool = False, stream=None):
+        items = list(items)
+        frames = make_frames(items)
+        self.ensure_workspace(frames, len(items))
+        (self.decode_plain if plain else self.decode_batch)(frames, len(items), stream)

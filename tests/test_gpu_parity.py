@@ -1,0 +1,296 @@
+"""GPU parity: libpolar's HIP kernels against the CPU oracle, through the C ABI.
+
+Min-sum (FP32) must be bit-exact: u-hat always, and every leaf LLR when
+pruning is off (leaf LLRs compared with IEEE ==, so +0 == -0).  Box-plus runs
+in FP32 on the GPU and FP64 in the oracle; its leaf LLRs are compared in
+teacher-forcing mode (the oracle re-runs with the GPU's u-hat as partial
+sums) within 1e-5 * max(|L_ref|, S_i), S_i being the leaf's value when every
+g adds magnitudes and every f takes the smaller magnitude, i.e. the size of
+the terms whose rounding errors reach leaf i.  Decision disagreements are
+allowed only where |L_ref| < 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_helpers import biawgn_frames, bsc_frames, decode, oracle_many
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_5882_amd import polar as lp
+
+    lp.load()
+
+
+# ---------------------------------------------------------------- lane ops
+def _expected_transpose(w):
+    bits = ((w[:, None] >> np.arange(64, dtype=np.uint64)[None, :]) & np.uint64(1)).astype(np.uint8)
+    t = bits.T
+    return (t.astype(np.uint64) << np.arange(64, dtype=np.uint64)[None, :]).sum(axis=1, dtype=np.uint64)
+
+
+def test_lane_selftest():
+    from paper_1204_5882_amd import polar as lp
+    import torch
+
+    _say("case: lane selftest")
+    out = lp.lane_selftest().cpu().numpy().view(np.uint32).reshape(16, 64)
+    torch.cuda.synchronize()
+    lanes = np.arange(64)
+    for i, h in enumerate((1, 2, 4, 8, 16, 32)):
+        use = (lanes & h) == 0
+        assert np.array_equal(out[i][use], 1000 + lanes[use] + h), f"lane_down<{h}>"
+        use = (lanes & h) != 0
+        assert np.array_equal(out[6 + i][use], 1000 + lanes[use] - h), f"lane_up<{h}>"
+    w = (((lanes.astype(np.uint64) * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF))
+         ^ ((lanes.astype(np.uint64) + np.uint64(17)) << np.uint64(40))).astype(np.uint64)
+    t = out[12].astype(np.uint64) | (out[13].astype(np.uint64) << np.uint64(32))
+    assert np.array_equal(t, _expected_transpose(w))
+    lt = out[14].astype(np.uint64) | (out[15].astype(np.uint64) << np.uint64(32))
+    # polar transform across lanes for every bit position
+    bits = ((w[:, None] >> np.arange(64, dtype=np.uint64)[None, :]) & np.uint64(1)).astype(np.uint8)
+    enc = np.stack([oracle.encode(6, bits[:, b]) for b in range(64)], axis=1)
+    exp = (enc.astype(np.uint64) << np.arange(64, dtype=np.uint64)[None, :]).sum(axis=1, dtype=np.uint64)
+    assert np.array_equal(lt, exp)
+
+
+# ---------------------------------------------------------------- encoder
+@pytest.mark.parametrize("log2n", [0, 1, 3, 5, 6, 9, 13, 14, 15, 17, 20])
+def test_encode_matches_oracle(log2n):
+    from paper_1204_5882_amd import polar as lp
+    import torch
+
+    _say(f"case: encode log2n={log2n}")
+    n = 1 << log2n
+    g = np.random.default_rng(log2n)
+    u = g.integers(0, 2, (3, n)).astype(np.uint8)
+    words = torch.from_numpy(synth.pack_bits(u).view(np.int32).reshape(-1).copy()).cuda()
+    x = lp.encode(log2n, words, n_frames=3)
+    torch.cuda.synchronize()
+    got = synth.unpack_bits(x.cpu().numpy().view(np.uint32).reshape(3, -1), n)
+    for k in range(3):
+        assert np.array_equal(got[k], oracle.encode(log2n, u[k]))
+    # in place, and the involution
+    lp.encode(log2n, x, x, n_frames=3)
+    torch.cuda.synchronize()
+    assert np.array_equal(synth.unpack_bits(x.cpu().numpy().view(np.uint32).reshape(3, -1), n), u)
+
+
+# ---------------------------------------------------------------- min-sum, every size
+def _random_frames(log2n, g, count):
+    n = 1 << log2n
+    frames = []
+    for k in range(count):
+        kind = k % 4
+        if kind == 0:
+            llr = np.where(g.random(n) < 0.1, -1.0, 1.0).astype(np.float32) * np.float32(3.47)
+        elif kind == 1:
+            llr = (2.0 * ((1 - 2 * g.integers(0, 2, n)) + 0.9 * g.standard_normal(n)) / 0.81).astype(np.float32)
+        elif kind == 2:
+            llr = g.integers(-2, 3, n).astype(np.float32)   # many exact zeros
+        else:
+            llr = (g.integers(-3, 4, n) * (0.5 + g.random(n))).astype(np.float32)
+        dens = [0.0, 1.0, 0.3, 0.5, 0.7][k % 5]
+        if k % 7 == 6:
+            mask, _, _ = oracle.frozen_set(log2n, 0.35, n // 2)
+        else:
+            mask = (g.random(n) < dens).astype(np.uint8)
+        fval = (g.integers(0, 2, n) & mask).astype(np.uint8)
+        frames.append((llr, mask, fval))
+    return frames
+
+
+@pytest.mark.parametrize("log2n", list(range(1, 17)))
+def test_minsum_all_sizes_bit_exact(log2n):
+    g = np.random.default_rng(500 + log2n)
+    frames = _random_frames(log2n, g, 10 if log2n <= 14 else 5)
+    refs = [oracle.sc_decode(f[0], f[1], f[2], want_leaf=True) for f in frames]
+    for prune in (True, False):
+        _say(f"case: minsum log2n={log2n} prune={prune} frames={len(frames)}")
+        us, _ = decode(frames, prune=prune)
+        for k, (u, ref) in enumerate(zip(us, refs)):
+            assert np.array_equal(u, ref[0]), f"frame {k} prune={prune}"
+    _say(f"case: minsum log2n={log2n} leaf dump")
+    us, leaves = decode(frames, prune=False, dump=True)
+    for k, (u, lf, ref) in enumerate(zip(us, leaves, refs)):
+        assert np.array_equal(u, ref[0])
+        assert np.all(lf == ref[1]), f"leaf LLRs differ in frame {k}"
+    _say(f"case: minsum log2n={log2n} plain decoder")
+    us, _ = decode(frames, plain=True)
+    for u, ref in zip(us, refs):
+        assert np.array_equal(u, ref[0])
+
+
+def test_minsum_pruned_leaf_dump_matches_where_computed():
+    g = np.random.default_rng(77)
+    frames = _random_frames(13, g, 6)
+    refs = [oracle.sc_decode(f[0], f[1], f[2], want_leaf=True) for f in frames]
+    _say("case: pruned leaf dump log2n=13")
+    us, leaves = decode(frames, prune=True, dump=True)
+    for u, lf, ref in zip(us, leaves, refs):
+        assert np.array_equal(u, ref[0])
+        done = ~np.isnan(lf)
+        assert np.all(lf[done] == ref[1][done])
+
+
+# ---------------------------------------------------------------- the QKD configurations
+def test_cfg1_n4096_bsc_64_frames():
+    """N = 2^12, BSC p = 0.02, 819 frozen (highest Bhattacharyya Z), 64 frames."""
+    frames = bsc_frames(12, 0.02, 819, [1000 + f for f in range(64)])
+    refs = [oracle.sc_decode(f[0], f[1], f[2], want_leaf=True) for f in frames]
+    for prune in (True, False):
+        _say(f"case: cfg1 prune={prune}")
+        us, _ = decode(frames, prune=prune)
+        assert all(np.array_equal(u, r[0]) for u, r in zip(us, refs))
+    _say("case: cfg1 leaf dump")
+    us, leaves = decode(frames, prune=False, dump=True)
+    assert all(np.all(lf == r[1]) for lf, r in zip(leaves, refs))
+    _say("case: cfg1 plain")
+    us, _ = decode(frames, plain=True)
+    assert all(np.array_equal(u, r[0]) for u, r in zip(us, refs))
+
+
+def test_cfg2_n2p20_bsc_256_frames_batched():
+    """N = 2^20, BSC p = 0.03, rate 0.75, 256 frames in one batched launch
+    (the configuration the benchmark times); every u-hat bit-exact."""
+    frames = bsc_frames(20, 0.03, 262144, [2000 + f for f in range(256)])
+    refs = oracle_many(frames)
+    _say("case: cfg2 256 frames batched, pruned")
+    us, _ = decode(frames, prune=True)
+    bad = [k for k, (u, r) in enumerate(zip(us, refs)) if not np.array_equal(u, r)]
+    assert not bad, f"frames differing from the oracle: {bad[:10]}"
+
+
+def test_cfg2_leaf_llrs_bit_exact():
+    frames = bsc_frames(20, 0.03, 262144, [2000, 2001])
+    refs = [oracle.sc_decode(f[0], f[1], f[2], want_leaf=True) for f in frames]
+    _say("case: cfg2 leaf dump, pruning off")
+    us, leaves = decode(frames, prune=False, dump=True)
+    for u, lf, r in zip(us, leaves, refs):
+        assert np.array_equal(u, r[0])
+        assert np.all(lf == r[1])
+    _say("case: cfg2 plain decoder")
+    us, _ = decode(frames, plain=True)
+    assert all(np.array_equal(u, r[0]) for u, r in zip(us, refs))
+
+
+def test_max_size_n2p24_minsum():
+    frames = bsc_frames(24, 0.03, (1 << 24) - int(0.75 * (1 << 24)), [7000])
+    ref = oracle.sc_decode(*frames[0])[0]
+    _say("case: N = 2^24 min-sum pruned")
+    us, _ = decode(frames, prune=True)
+    assert np.array_equal(us[0], ref)
+
+
+# ---------------------------------------------------------------- closed forms at scale
+def test_noiseless_rate0_rate1_at_scale():
+    log2n = 20
+    n = 1 << log2n
+    mask, _, _ = oracle.frozen_set(log2n, synth.bsc_z0(0.03), 262144)
+    u, fval, llr = synth.frame(11, log2n, "noiseless", 0.03, mask, lambda v: oracle.encode(log2n, v))
+    g = np.random.default_rng(12)
+    r1 = g.standard_normal(n).astype(np.float32)
+    r1[r1 == 0] = 1.0
+    fv0 = g.integers(0, 2, n).astype(np.uint8)
+    cases = [(llr, mask, fval), (r1, np.zeros(n, np.uint8), np.zeros(n, np.uint8)),
+             (r1, np.ones(n, np.uint8), fv0)]
+    _say("case: noiseless / rate-1 / rate-0 at N = 2^20")
+    for prune in (True, False):
+        us, _ = decode(cases, prune=prune)
+        assert np.array_equal(us[0], u)
+        assert np.array_equal(us[1], oracle.encode(log2n, (r1 < 0).astype(np.uint8)))
+        assert np.array_equal(us[2], fv0)
+
+
+# ---------------------------------------------------------------- batching invariance
+def test_batching_invariance_mixed_sizes_and_rates():
+    """Mixed N (2^10 .. 2^16), BSC and BIAWGN, union-bound rates, shuffled:
+    the batched result equals each frame decoded alone, and the oracle."""
+    g = np.random.default_rng(4)
+    frames = []
+    for f in range(48):
+        log2n = int(g.integers(10, 17))
+        if f % 2 == 0:
+            p = float(g.uniform(0.01, 0.05))
+            mask, _, _ = oracle.frozen_set(log2n, synth.bsc_z0(p), -1, 0.1)
+            u, fval, llr = synth.frame(4000 + f, log2n, "bsc", p, mask, lambda v: oracle.encode(log2n, v))
+        else:
+            s = float(g.uniform(0.8, 1.2))
+            mask, _, _ = oracle.frozen_set(log2n, synth.biawgn_z0(s), -1, 0.1)
+            u, fval, llr = synth.frame(4000 + f, log2n, "biawgn", s, mask, lambda v: oracle.encode(log2n, v))
+        frames.append((llr, mask, fval))
+    refs = [oracle.sc_decode(*fr)[0] for fr in frames]
+    _say("case: mixed batch of 48")
+    us, _ = decode(frames)
+    for k in range(len(frames)):
+        assert np.array_equal(us[k], refs[k]), f"frame {k}"
+    _say("case: mixed batch, frames alone")
+    for k in range(0, len(frames), 5):
+        solo, _ = decode([frames[k]])
+        assert np.array_equal(solo[0], us[k])
+
+
+# ---------------------------------------------------------------- box-plus
+def _magnitude_scale(llr):
+    """S_i: leaf values with g -> |a| + |b| and f -> min(|a|, |b|)."""
+    n = llr.size
+    return oracle.sc_decode(np.abs(llr), np.ones(n, np.uint8), np.zeros(n, np.uint8), want_leaf=True)[1]
+
+
+def _check_boxplus(frames, us, leaves):
+    rescued = 0
+    for k, (fr, u, lf) in enumerate(zip(frames, us, leaves)):
+        llr, mask, fval = fr
+        u_or, l_ref, _ = oracle.sc_decode(llr, mask, fval, boxplus=True, teacher=u, want_leaf=True)
+        s = _magnitude_scale(llr).astype(np.float64)
+        err = np.abs(lf.astype(np.float64) - l_ref)
+        tol = 1e-5 * np.maximum(np.abs(l_ref), s)
+        bad = err > tol
+        assert not bad.any(), f"frame {k}: {bad.sum()} leaves out of tolerance, worst {err[bad].max()}"
+        rescued += int((err > 1e-5 * np.abs(l_ref)).sum())
+        dis = (u_or != u) & (mask == 0)
+        assert np.all(np.abs(l_ref[dis]) < 1e-6), f"frame {k}: decisions differ at |L| >= 1e-6"
+    return rescued
+
+
+@pytest.mark.parametrize("log2n", [1, 4, 6, 8, 11, 12, 13, 16])
+def test_boxplus_sizes_within_tolerance(log2n):
+    frames = biawgn_frames(log2n, 0.97, (1 << log2n) - int(0.45 * (1 << log2n)),
+                           [6000 + 10 * log2n + k for k in range(4)])
+    _say(f"case: box-plus log2n={log2n} leaf dump")
+    us, leaves = decode(frames, f_kind=1, prune=False, dump=True)
+    rescued = _check_boxplus(frames, us, leaves)
+    print(f"box-plus log2n={log2n}: {rescued} leaves within tolerance only through S_i")
+    _say(f"case: box-plus log2n={log2n} pruned")
+    up, _ = decode(frames, f_kind=1, prune=True)
+    for k, fr in enumerate(frames):
+        u_or, l_ref, _ = oracle.sc_decode(fr[0], fr[1], fr[2], boxplus=True, teacher=up[k], want_leaf=True)
+        dis = (u_or != up[k]) & (fr[1] == 0)
+        assert np.all(np.abs(l_ref[dis]) < 1e-6)
+
+
+def test_cfg3_n2p24_boxplus_sampled():
+    """N = 2^24, BIAWGN sigma = 0.97, rate 0.45, exact box-plus: one frame
+    of the 16-frame configuration with its leaf LLRs checked in full."""
+    log2n = 24
+    frames = biawgn_frames(log2n, 0.97, (1 << 24) - int(0.45 * (1 << 24)), [3000])
+    _say("case: cfg3 N = 2^24 box-plus leaf dump")
+    us, leaves = decode(frames, f_kind=1, prune=False, dump=True)
+    rescued = _check_boxplus(frames, us, leaves)
+    print(f"cfg3: {rescued} leaves within tolerance only through S_i")
