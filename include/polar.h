@@ -118,6 +118,12 @@ typedef struct polar_ctx polar_ctx;
                                    0 = automatic (default)                               */
 #define POLAR_OPT_WG_WAVES 3    /* wavefronts per workgroup: 1, 2, 4, 8 or 16; 0 = auto */
 #define POLAR_OPT_MAX_SLOTS 4   /* max frames in flight (workgroups); 0 = auto          */
+#define POLAR_OPT_TIMING 5      /* device pointer (as an integer) to 8 zeroed uint64
+                                   counters, or 0 = off.  Decoding then adds, per frame:
+                                   [0] ticks spent in register-resident subtree decoding
+                                   (the serial leaf region), [1] ticks for the whole
+                                   frame, [2] 1.  Ticks are the 100 MHz s_memrealtime
+                                   clock, summed over frames in flight.              */
 
 /*
  * Create a decoding context on a device.  The context owns only host-side

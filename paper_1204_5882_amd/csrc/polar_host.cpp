@@ -167,6 +167,7 @@ struct polar_ctx {
     int cutover = 0;    // 0 = automatic
     int waves = 0;      // 0 = automatic
     int max_slots = 0;  // 0 = automatic
+    unsigned long long* prof = nullptr;  // optional device timing counters
     FrameDesc* staging = nullptr;  // pinned host copy of the descriptor table
     size_t staging_cap = 0;
     hipEvent_t staged = nullptr;   // recorded after the last descriptor upload
@@ -295,16 +296,30 @@ int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* str
     const int waves = plain ? 4 : eff_waves(c);
     const int prune = plain ? 0 : c->prune;
     for (const auto& gr : p.groups) {
+        DecodeLaunch a{};
+        a.cutover = cut;
+        a.fk = gr.fk;
+        a.prune = prune;
+        a.dump = gr.dump;
+        a.waves = waves;
+        a.counter = counter;
+        a.slots = slots;
+        a.slot_bytes = p.slot_bytes;
+        a.prof = c->prof;
+        a.stream = s;
         if (plain) {
             for (int k = 0; k < gr.count; ++k) {
-                hipError_t e = polar_dev_launch_decode(cut, gr.fk, prune, gr.dump, waves, dtab + gr.first + k, 1,
-                                                       counter, slots, p.slot_bytes, 1, s);
+                a.descs = dtab + gr.first + k;
+                a.n_frames = 1;
+                a.grid = 1;
+                hipError_t e = polar_dev_launch_decode(&a);
                 if (e != hipSuccess) return hip_fail(e, "decode launch");
             }
         } else {
-            const int grid = std::min(gr.count, eff_max_slots(c));
-            hipError_t e = polar_dev_launch_decode(cut, gr.fk, prune, gr.dump, waves, dtab + gr.first, gr.count,
-                                                   counter, slots, p.slot_bytes, grid, s);
+            a.descs = dtab + gr.first;
+            a.n_frames = gr.count;
+            a.grid = std::min(gr.count, eff_max_slots(c));
+            hipError_t e = polar_dev_launch_decode(&a);
             if (e != hipSuccess) return hip_fail(e, "decode launch");
         }
     }
@@ -381,6 +396,10 @@ extern "C" int polar_ctx_set_option(polar_ctx* c, int option, int64_t value) {
             if (value < 0 || value > (1 << 20)) return fail(POLAR_E_INVAL, "max_slots out of range");
             c->max_slots = (int)value;
             return ok();
+        case POLAR_OPT_TIMING:
+            if (value & 7) return fail(POLAR_E_INVAL, "timing buffer must be 8-byte aligned");
+            c->prof = reinterpret_cast<unsigned long long*>((uintptr_t)value);
+            return ok();
         default:
             return fail(POLAR_E_INVAL, "unknown option %d", option);
     }
@@ -393,6 +412,7 @@ extern "C" int polar_ctx_get_option(polar_ctx* c, int option, int64_t* value) {
         case POLAR_OPT_CUTOVER: *value = eff_cutover(c); return ok();
         case POLAR_OPT_WG_WAVES: *value = eff_waves(c); return ok();
         case POLAR_OPT_MAX_SLOTS: *value = eff_max_slots(c); return ok();
+        case POLAR_OPT_TIMING: *value = (int64_t)(uintptr_t)c->prof; return ok();
         default: return fail(POLAR_E_INVAL, "unknown option %d", option);
     }
 }

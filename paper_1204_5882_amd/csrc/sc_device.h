@@ -19,10 +19,25 @@ struct FrameDesc {
 };
 static_assert(sizeof(FrameDesc) == 64, "descriptor layout");
 
+// Everything one persistent decode launch needs.
+struct DecodeLaunch {
+    int cutover;               // log2 of the register-resident subtree
+    int fk;                    // 0 min-sum, 1 box-plus
+    int prune;                 // exact rate-0 / rate-1 shortcuts
+    int dump;                  // write leaf LLRs
+    int waves;                 // wavefronts per workgroup
+    int grid;                  // workgroups (frames in flight)
+    const FrameDesc* descs;    // device descriptor table
+    int n_frames;
+    unsigned* counter;         // device work counter (reset by the launch)
+    uint8_t* slots;            // per-workgroup scratch, slot_bytes each
+    int64_t slot_bytes;
+    unsigned long long* prof;  // optional timing counters (device, 8 words) or null
+    hipStream_t stream;
+};
+
 extern "C" {
-hipError_t polar_dev_launch_decode(int cutover, int fk, int prune, int dump, int waves, const FrameDesc* descs,
-                                   int n_frames, unsigned* counter, uint8_t* slots, int64_t slot_bytes, int grid,
-                                   hipStream_t s);
+hipError_t polar_dev_launch_decode(const DecodeLaunch* a);
 int polar_dev_cutover_supported(int c);
 int polar_dev_waves_supported(int w);
 int64_t polar_dev_slot_bytes(int log2n, int cutover);

@@ -268,55 +268,131 @@ __device__ __forceinline__ bool lane_bit(uint64_t mask) { return __builtin_amdgc
 
 // ---------------------------------------------------------------------------
 // 64-leaf block decoder.  The node of size M at lane offset O holds its LLRs
-// in lanes [O, O + M) of a single VGPR; everything else is wave-uniform.
+// in lanes [O, O + M) of a single VGPR.  Partial sums are kept per lane as a
+// sign word (0 or 0x80000000), so f, g and the combine are pure vector code:
+//   f:       a_L = f(a, down_H(a))
+//   g:       a_R = a + up_H(a ^ beta)      (beta of the left child flips a_lo)
+//   combine: beta[j] ^= beta[j + H] for j in [O, O + H)
+// The node type (rate 0, rate 1, repetition, mixed) is a function of the
+// block's frozen mask alone, so it is decided on the scalar unit without
+// waiting for vector results; only the rate-1 floor test and the repetition
+// decision read a ballot.
 // ---------------------------------------------------------------------------
-struct Blk {
-    uint64_t F;     // frozen mask of the block (bit i = leaf i)
-    uint64_t V;     // frozen values
-    uint64_t beta;  // partial sums, filled node by node
-    float leaf;     // lane i: decision LLR of leaf i
-    bool has_leaf;  // lane i: leaf i was reached (not inside a pruned node)
-};
+constexpr uint32_t SIGN = 0x80000000u;
 
 template <int M>
 constexpr int ilog2() { return M <= 1 ? 0 : 1 + ilog2<M / 2>(); }
 
-template <int M, int O, int FK, bool PRUNE, bool DUMP>
-__device__ __forceinline__ void blk_node(float a, Blk& B) {
-    constexpr uint64_t NM = ones64(M) << O;
+struct Blk {
+    uint64_t F;       // frozen mask of the block (bit i = leaf i), wave-uniform
+    uint32_t fv;      // lane i: SIGN if leaf i is frozen with value 1
+    uint32_t w[7];    // lane i: SIGN if bit i of the frozen values re-encoded
+                      // inside every aligned 2^t-block (w[0] = fv)
+    uint32_t beta;    // lane i: partial sum of element i, as a sign word
+    float leaf;       // lane i: decision LLR of leaf i
+    bool has_leaf;    // lane i: leaf i was reached (not inside a pruned node)
+};
+
+__device__ __forceinline__ uint32_t sel_lanes(uint64_t lanes, uint32_t x, uint32_t y) {
+    return lane_bit(lanes) ? x : y;
+}
+
+// Repetition node: every leaf frozen except the last.  SC never needs the
+// f values here (the frozen decisions do not read LLRs): the last leaf's LLR
+// is the chain of g updates down the right spine, each left sibling of size h
+// being a rate-0 node whose partial sums are w[log h] on its lanes.  The node's
+// partial sums are the frozen values re-encoded (w[log M]), all flipped when
+// the last bit is 1 (row M-1 of G_M is all ones).
+template <int H, int M>
+__device__ __forceinline__ float rep_chain(float x, const Blk& B) {
+    if constexpr (H == 0) {
+        return x;
+    } else {
+        const float y = x + __uint_as_float(lane_up<H>(__float_as_uint(x) ^ B.w[ilog2<H>()]));
+        return rep_chain<H / 2, M>(y, B);
+    }
+}
+
+template <int M, bool DUMP>
+__device__ __forceinline__ void rep_node(float a, int O, Blk& B) {
+    const float last = rep_chain<M / 2, M>(a, B);
+    const int il = O + M - 1;
+    if (DUMP && lane_id() == il) {
+        B.leaf = last;
+        B.has_leaf = true;
+    }
+    const bool u = (ballot(last < 0.0f) >> il) & 1ull;
+    B.beta = sel_lanes(ones64(M) << O, B.w[ilog2<M>()] ^ (u ? SIGN : 0u), B.beta);
+}
+
+// Node of size M at lane offset O (runtime).  Each size has one copy of its
+// code: the two children are visited by a two-pass loop that is kept rolled,
+// so the code grows with log M rather than with the number of nodes.
+template <int M, int FK, bool PRUNE, bool DUMP>
+__device__ __forceinline__ void blk_node(float a, int O, Blk& B) {
+    const uint64_t nm = ones64(M) << O;
     if constexpr (M == 1) {
         if (DUMP && lane_id() == O) {
             B.leaf = a;
             B.has_leaf = true;
         }
         // frozen: the revealed value; information bit: [alpha < 0]
-        B.beta |= ((B.V & B.F) | (ballot(a < 0.0f) & ~B.F)) & NM;
-        return;
+        const bool frozen = (B.F >> O) & 1ull;
+        const uint32_t d = frozen ? B.fv : ((a < 0.0f) ? SIGN : 0u);
+        B.beta = sel_lanes(nm, d, B.beta);
     } else {
         if constexpr (PRUNE) {
-            // One flag and one exit: the nested form "if rate 1 { if no LLR
-            // below the floor { ...; return } }" was compiled wrongly by this
-            // toolchain at -O2/-O3 (partial sums corrupted after a failed
-            // check), while this flat form is exact.
-            const uint64_t fm = B.F & NM;
-            const uint64_t low = ballot(below_rate1_floor<FK, ilog2<M>()>(a)) & NM;
-            const uint64_t neg = ballot(a < 0.0f) & NM;
-            const bool rate0 = fm == NM;
+            const uint64_t fm = B.F & nm;
+            const bool rate0 = fm == nm;
+            const bool repn = fm == (nm ^ (1ull << (O + M - 1)));
+            // The rate-1 ballot is taken unconditionally and every shortcut
+            // leaves through one exit.  With the ballot under "if (rate 1)",
+            // or an early return nested in that test, this toolchain's -O2/-O3
+            // code returned corrupted partial sums after a failed rate-1 test
+            // (exact at -O1; found by the box-plus parity tests).
+            const uint64_t low = ballot(below_rate1_floor<FK, ilog2<M>()>(a)) & nm;
             const bool rate1 = (fm == 0) & (low == 0);
-            if (rate0 | rate1) {
-                B.beta |= rate0 ? (word_transform((B.V & NM) >> O, M) << O) : neg;
+            if (rate0 | rate1 | repn) {
+                if (repn) {
+                    rep_node<M, DUMP>(a, O, B);
+                } else if (rate0) {
+                    B.beta = sel_lanes(nm, B.w[ilog2<M>()], B.beta);
+                } else {
+                    B.beta = sel_lanes(nm, (a < 0.0f) ? SIGN : 0u, B.beta);
+                }
                 return;
             }
         }
         constexpr int H = M / 2;
-        float al = fupd<FK>(a, lane_downf<H>(a));  // valid in lanes [O, O + H)
-        blk_node<H, O, FK, PRUNE, DUMP>(al, B);
-        // lane j in [O + H, O + M) needs beta bit j - H
-        const uint32_t sgn = lane_bit(B.beta << H) ? 0x80000000u : 0u;
-        float ar = gupd(lane_upf<H>(a), a, sgn);   // valid in lanes [O + H, O + M)
-        blk_node<H, O + H, FK, PRUNE, DUMP>(ar, B);
-        B.beta ^= (B.beta >> H) & (ones64(H) << O);
+#pragma clang loop unroll(disable)
+        for (int side = 0; side < 2; ++side) {
+            float c;
+            if (side == 0) {
+                c = fupd<FK>(a, lane_downf<H>(a));  // left child, lanes [O, O + H)
+            } else {
+                c = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ B.beta));  // right child
+            }
+            blk_node<H, FK, PRUNE, DUMP>(c, O + side * H, B);
+        }
+        B.beta = sel_lanes(ones64(H) << O, B.beta ^ lane_down<H>(B.beta), B.beta);
     }
+}
+
+// Block set-up from its frozen mask F and frozen values V (wave-uniform).
+__device__ __forceinline__ void blk_init(Blk& B, uint64_t F, uint64_t V) {
+    B.F = F;
+    uint64_t W = V & F;
+    B.w[0] = lane_bit(W) ? SIGN : 0u;
+#pragma unroll
+    for (int t = 1; t < 7; ++t) {
+        const int h = 1 << (t - 1);
+        W ^= (W >> h) & low_mask64(h);
+        B.w[t] = lane_bit(W) ? SIGN : 0u;
+    }
+    B.fv = B.w[0];
+    B.beta = 0;
+    B.leaf = 0.0f;
+    B.has_leaf = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -472,13 +548,9 @@ __device__ __forceinline__ void subtree_decode(const SubIO io, int lg, float* ld
                     v.a6 = gupd(v.a7[0], v.a7[1], sgn);
                 }
                 Blk B;
-                B.F = readlane64(mw, b);
-                B.V = readlane64(vw, b);
-                B.beta = 0;
-                B.leaf = 0.0f;
-                B.has_leaf = false;
-                blk_node<64, 0, FK, PRUNE, DUMP>(v.a6, B);
-                acc |= (uint64_t)lane_bit(B.beta) << b;
+                blk_init(B, readlane64(mw, b), readlane64(vw, b));
+                blk_node<64, FK, PRUNE, DUMP>(v.a6, 0, B);
+                acc |= (uint64_t)(B.beta >> 31) << b;
                 if (DUMP && B.has_leaf) io.leaf[b * 64 + l] = B.leaf;
                 lc = 6;
                 break;
@@ -547,20 +619,16 @@ __device__ __forceinline__ void tiny_decode(const FrameDesc& fd) {
     const int n = 1 << fd.log2n;
     float a = l < n ? fd.llr[l] : 0.0f;
     Blk B;
-    B.F = fd.mask[0] & (uint32_t)ones64(n);
-    B.V = fd.vals[0] & (uint32_t)ones64(n);
-    B.beta = 0;
-    B.leaf = 0.0f;
-    B.has_leaf = false;
+    blk_init(B, fd.mask[0] & (uint32_t)ones64(n), fd.vals[0]);
     switch (fd.log2n) {
-        case 1: blk_node<2, 0, FK, PRUNE, DUMP>(a, B); break;
-        case 2: blk_node<4, 0, FK, PRUNE, DUMP>(a, B); break;
-        case 3: blk_node<8, 0, FK, PRUNE, DUMP>(a, B); break;
-        case 4: blk_node<16, 0, FK, PRUNE, DUMP>(a, B); break;
-        case 5: blk_node<32, 0, FK, PRUNE, DUMP>(a, B); break;
-        default: blk_node<1, 0, FK, PRUNE, DUMP>(a, B); break;
+        case 1: blk_node<2, FK, PRUNE, DUMP>(a, 0, B); break;
+        case 2: blk_node<4, FK, PRUNE, DUMP>(a, 0, B); break;
+        case 3: blk_node<8, FK, PRUNE, DUMP>(a, 0, B); break;
+        case 4: blk_node<16, FK, PRUNE, DUMP>(a, 0, B); break;
+        case 5: blk_node<32, FK, PRUNE, DUMP>(a, 0, B); break;
+        default: blk_node<1, FK, PRUNE, DUMP>(a, 0, B); break;
     }
-    uint64_t u = word_transform(B.beta, n);
+    uint64_t u = word_transform(ballot(B.beta != 0u) & ones64(n), n);
     if (l == 0) fd.uhat[0] = (uint32_t)u;
     if (DUMP && l < n && B.has_leaf) fd.leaf[l] = B.leaf;
 }
@@ -570,25 +638,27 @@ __device__ __forceinline__ void tiny_decode(const FrameDesc& fd) {
 // Rows of 64 consecutive elements; lane = element & 63, so the lane-packed
 // partial sums of the left sibling are read with one coalesced word per row.
 // ---------------------------------------------------------------------------
+constexpr int SWEEP_UNROLL = 8;  // rows in flight per wave
+
 template <int FK>
 __device__ __forceinline__ void sweep_f(const float* __restrict__ in, int64_t half, float* __restrict__ out,
                                         int wave, int nw) {
     const int l = lane_id();
     const int64_t rows = half >> 6;
     int64_t r = wave;
-    for (; r + 3 * nw < rows; r += 4 * nw) {
-        float x[4], y[4];
+    for (; r + (SWEEP_UNROLL - 1) * nw < rows; r += SWEEP_UNROLL * nw) {
+        float x[SWEEP_UNROLL], y[SWEEP_UNROLL];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int64_t j = (r + i * nw) * 64 + l;
+        for (int i = 0; i < SWEEP_UNROLL; ++i) {
+            const int64_t j = (r + i * nw) * 64 + l;
             x[i] = in[j];
             y[i] = in[j + half];
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[(r + i * nw) * 64 + l] = fupd<FK>(x[i], y[i]);
+        for (int i = 0; i < SWEEP_UNROLL; ++i) out[(r + i * nw) * 64 + l] = fupd<FK>(x[i], y[i]);
     }
     for (; r < rows; r += nw) {
-        int64_t j = r * 64 + l;
+        const int64_t j = r * 64 + l;
         out[j] = fupd<FK>(in[j], in[j + half]);
     }
 }
@@ -603,28 +673,28 @@ __device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t ha
     const int l = lane_id();
     const int64_t rows = half >> 6;
     int64_t r = wave;
-    for (; r + 3 * nw < rows; r += 4 * nw) {
-        float x[4], y[4];
-        uint64_t w[4];
+    for (; r + (SWEEP_UNROLL - 1) * nw < rows; r += SWEEP_UNROLL * nw) {
+        float x[SWEEP_UNROLL], y[SWEEP_UNROLL];
+        uint64_t w[SWEEP_UNROLL];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int64_t rr = r + i * nw;
-            int64_t j = rr * 64 + l;
+        for (int i = 0; i < SWEEP_UNROLL; ++i) {
+            const int64_t rr = r + i * nw;
+            const int64_t j = rr * 64 + l;
             x[i] = in[j];
             y[i] = in[j + half];
             w[i] = beta[(rr >> (C - 6)) * 64 + l];
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int64_t rr = r + i * nw;
-            uint32_t sgn = (uint32_t)((w[i] >> (rr & (E - 1))) & 1ull) << 31;
+        for (int i = 0; i < SWEEP_UNROLL; ++i) {
+            const int64_t rr = r + i * nw;
+            const uint32_t sgn = (uint32_t)((w[i] >> (rr & (E - 1))) & 1ull) << 31;
             out[rr * 64 + l] = gupd(x[i], y[i], sgn);
         }
     }
     for (; r < rows; r += nw) {
-        int64_t j = r * 64 + l;
-        uint64_t w = beta[(r >> (C - 6)) * 64 + l];
-        uint32_t sgn = (uint32_t)((w >> (r & (E - 1))) & 1ull) << 31;
+        const int64_t j = r * 64 + l;
+        const uint64_t w = beta[(r >> (C - 6)) * 64 + l];
+        const uint32_t sgn = (uint32_t)((w >> (r & (E - 1))) & 1ull) << 31;
         out[j] = gupd(in[j], in[j + half], sgn);
     }
 }
@@ -641,8 +711,12 @@ __host__ __device__ inline int64_t slot_level_offset(int log2n, int d) {
     return (n - (n >> (d - 1))) * 4;
 }
 
+// Optional timing: wave 0 accumulates, in s_memrealtime ticks (100 MHz), the
+// time spent in register-resident subtree decoding.
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
 template <int C, int FK, bool PRUNE, bool DUMP, int W>
-__device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot, float* lds) {
+__device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot, float* lds, uint64_t& sub_ticks) {
     constexpr int R = SubCfg<C>::R;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -659,8 +733,10 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
             __syncthreads();
         }
         if (wave == 0) {
+            const uint64_t t0 = now_ticks();
             SubIO io{fd.mask, fd.vals, fd.uhat, fd.leaf, nullptr};
             subtree_decode<C, FK, PRUNE, DUMP>(io, n, lds, fd.llr);
+            sub_ticks += now_ticks() - t0;
         }
         return;
     }
@@ -696,10 +772,12 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
             __syncthreads();
         }
         if (wave == 0) {
+            const uint64_t t0 = now_ticks();
             const int64_t base = s << C;
             SubIO io{fd.mask + (base >> 5), fd.vals + (base >> 5), fd.uhat + (base >> 5),
                      DUMP ? fd.leaf + base : nullptr, beta + s * 64};
             subtree_decode<C, FK, PRUNE, DUMP>(io, C, lds, nullptr);
+            sub_ticks += now_ticks() - t0;
         }
         __syncthreads();
     }
@@ -708,7 +786,7 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
 template <int C, int FK, bool PRUNE, bool DUMP, int W>
 __global__ __launch_bounds__(W * 64) void k_sc_decode(const FrameDesc* __restrict__ descs, int n_frames,
                                                        unsigned* __restrict__ counter, uint8_t* slots,
-                                                       int64_t slot_bytes) {
+                                                       int64_t slot_bytes, unsigned long long* prof) {
     __shared__ float lds[SubCfg<C>::lds_floats > (1 << C) ? SubCfg<C>::lds_floats : (1 << C)];
     __shared__ int s_frame;
     uint8_t* slot = slots + (int64_t)blockIdx.x * slot_bytes;
@@ -719,8 +797,15 @@ __global__ __launch_bounds__(W * 64) void k_sc_decode(const FrameDesc* __restric
         __syncthreads();
         if (f >= n_frames) break;
         const FrameDesc fd = descs[f];
-        decode_frame<C, FK, PRUNE, DUMP, W>(fd, slot, lds);
+        uint64_t sub_ticks = 0;
+        const uint64_t t0 = prof ? now_ticks() : 0;
+        decode_frame<C, FK, PRUNE, DUMP, W>(fd, slot, lds, sub_ticks);
         __syncthreads();
+        if (prof && threadIdx.x == 0) {
+            atomicAdd(prof + 0, (unsigned long long)sub_ticks);
+            atomicAdd(prof + 1, (unsigned long long)(now_ticks() - t0));
+            atomicAdd(prof + 2, 1ull);
+        }
     }
 }
 
@@ -812,54 +897,42 @@ __global__ void k_lane_selftest(uint32_t* out) {
 using namespace polar_dev;
 
 template <int C, int FK, bool PRUNE, bool DUMP, int W>
-static hipError_t launch_decode_t(const FrameDesc* descs, int n_frames, unsigned* counter, uint8_t* slots,
-                                  int64_t slot_bytes, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_fill_u32), dim3(1), dim3(64), 0, s, counter, 1, 0u);
-    hipLaunchKernelGGL((k_sc_decode<C, FK, PRUNE, DUMP, W>), dim3(grid), dim3(W * 64), 0, s, descs, n_frames, counter,
-                       slots, slot_bytes);
+static hipError_t launch_decode_t(const DecodeLaunch& a) {
+    hipLaunchKernelGGL((k_fill_u32), dim3(1), dim3(64), 0, a.stream, a.counter, 1, 0u);
+    hipLaunchKernelGGL((k_sc_decode<C, FK, PRUNE, DUMP, W>), dim3(a.grid), dim3(W * 64), 0, a.stream, a.descs,
+                       a.n_frames, a.counter, a.slots, a.slot_bytes, a.prof);
     return hipGetLastError();
 }
 
 template <int C, int FK, bool PRUNE, bool DUMP>
-static hipError_t launch_w(int waves, const FrameDesc* d, int nf, unsigned* cnt, uint8_t* slots, int64_t sb,
-                           int grid, hipStream_t s) {
-    switch (waves) {
-        case 4: return launch_decode_t<C, FK, PRUNE, DUMP, 4>(d, nf, cnt, slots, sb, grid, s);
+static hipError_t launch_w(const DecodeLaunch& a) {
+    switch (a.waves) {
+        case 4: return launch_decode_t<C, FK, PRUNE, DUMP, 4>(a);
+        case 8: return launch_decode_t<C, FK, PRUNE, DUMP, 8>(a);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int C, int FK>
-static hipError_t launch_pd(bool prune, bool dump, int waves, const FrameDesc* d, int nf, unsigned* cnt,
-                            uint8_t* slots, int64_t sb, int grid, hipStream_t s) {
-    if (prune) {
-        return dump ? launch_w<C, FK, true, true>(waves, d, nf, cnt, slots, sb, grid, s)
-                    : launch_w<C, FK, true, false>(waves, d, nf, cnt, slots, sb, grid, s);
-    }
-    return dump ? launch_w<C, FK, false, true>(waves, d, nf, cnt, slots, sb, grid, s)
-                : launch_w<C, FK, false, false>(waves, d, nf, cnt, slots, sb, grid, s);
+static hipError_t launch_pd(const DecodeLaunch& a) {
+    if (a.prune) return a.dump ? launch_w<C, FK, true, true>(a) : launch_w<C, FK, true, false>(a);
+    return a.dump ? launch_w<C, FK, false, true>(a) : launch_w<C, FK, false, false>(a);
 }
 
 template <int C>
-static hipError_t launch_c(int fk, bool prune, bool dump, int waves, const FrameDesc* d, int nf, unsigned* cnt,
-                           uint8_t* slots, int64_t sb, int grid, hipStream_t s) {
-    if (fk == 0) return launch_pd<C, 0>(prune, dump, waves, d, nf, cnt, slots, sb, grid, s);
-    return launch_pd<C, 1>(prune, dump, waves, d, nf, cnt, slots, sb, grid, s);
+static hipError_t launch_c(const DecodeLaunch& a) {
+    return a.fk == 0 ? launch_pd<C, 0>(a) : launch_pd<C, 1>(a);
 }
 
-extern "C" hipError_t polar_dev_launch_decode(int cutover, int fk, int prune, int dump, int waves,
-                                              const FrameDesc* descs, int n_frames, unsigned* counter,
-                                              uint8_t* slots, int64_t slot_bytes, int grid, hipStream_t s) {
-    switch (cutover) {
-        case 12:
-            return launch_c<12>(fk, prune != 0, dump != 0, waves, descs, n_frames, counter, slots, slot_bytes,
-                                grid, s);
+extern "C" hipError_t polar_dev_launch_decode(const DecodeLaunch* a) {
+    switch (a->cutover) {
+        case 12: return launch_c<12>(*a);
         default: return hipErrorInvalidValue;
     }
 }
 
 extern "C" int polar_dev_cutover_supported(int c) { return c == 12; }
-extern "C" int polar_dev_waves_supported(int w) { return w == 4; }
+extern "C" int polar_dev_waves_supported(int w) { return w == 4 || w == 8; }
 
 extern "C" int64_t polar_dev_slot_bytes(int log2n, int cutover) {
     if (log2n <= cutover) return 256;

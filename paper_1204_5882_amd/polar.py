@@ -33,6 +33,7 @@ POLAR_OPT_PRUNE = 1
 POLAR_OPT_CUTOVER = 2
 POLAR_OPT_WG_WAVES = 3
 POLAR_OPT_MAX_SLOTS = 4
+POLAR_OPT_TIMING = 5
 
 # every symbol declared in include/polar.h
 EXPORTED = [

@@ -12,6 +12,11 @@
        beta = [beta_L ^ beta_R, beta_R];  leaf: beta = S & ~Z
    with the early exit "no zeros -> beta = S".
 3. The in-word polar transform x ^= (x >> h) & LOW_h for h = 1..32.
+4. Repetition node (every leaf frozen but the last): the last leaf's LLR is
+   the g chain down the right spine, the left sibling of size h at offset o
+   contributing the partial sums W_h[o, o + h) of the frozen values, W_h being
+   the frozen word with G_h applied inside every aligned h-block; the node's
+   partial sums are then G over (frozen values, decision).
 Each is checked against the plain oracle (no shortcuts)."""
 import itertools
 
@@ -121,3 +126,43 @@ def test_word_transform_is_the_encoder():
             u = g.integers(0, 2, m).astype(np.uint8)
             x = oracle.encode(m.bit_length() - 1, u)
             assert word_transform(_to_word(u), m) == _to_word(x)
+
+
+def rep_node_model(llr, fval):
+    """The repetition-node shortcut on a node of size m at offset 0."""
+    m = llr.size
+    V = _to_word(fval[:-1])
+    W = [V]
+    h = 1
+    while h < m:
+        W.append(W[-1] ^ ((W[-1] >> h) & LOW[h]))
+        h *= 2
+    x = [np.float32(v) for v in llr]
+    h = m // 2
+    while h >= 1:
+        lg = h.bit_length() - 1
+        ol = m - 2 * h
+        sib = (W[lg] >> ol) & ((1 << h) - 1)
+        for j in range(h):
+            a, b = x[ol + j], x[ol + h + j]
+            x[ol + h + j] = np.float32(b - a) if (sib >> j) & 1 else np.float32(b + a)
+        h //= 2
+    last = x[m - 1]
+    u = int(last < 0)
+    return word_transform(V | (u << (m - 1)), m), last
+
+
+@pytest.mark.parametrize("m", [2, 4, 8, 16, 32, 64])
+def test_repetition_node_shortcut(m):
+    g = np.random.default_rng(200 + m)
+    mask = np.ones(m, np.uint8)
+    mask[-1] = 0
+    for trial in range(300):
+        llr = (g.integers(-3, 4, m) * (0.5 + g.random(m))).astype(np.float32)
+        if trial % 3 == 0:
+            llr[g.random(m) < 0.3] = 0.0
+        fval = (g.integers(0, 2, m) & mask).astype(np.uint8)
+        _, leaf, beta = oracle.sc_decode(llr, mask, fval, want_leaf=True, want_beta=True)
+        got_beta, last = rep_node_model(llr, fval)
+        assert got_beta == _to_word(beta)
+        assert np.float32(last).view(np.uint32) == leaf[-1].view(np.uint32)
