@@ -285,6 +285,10 @@ constexpr int ilog2() { return M <= 1 ? 0 : 1 + ilog2<M / 2>(); }
 
 struct Blk {
     uint64_t F;       // frozen mask of the block (bit i = leaf i), wave-uniform
+    uint64_t V;       // frozen values of the block (zero outside F), wave-uniform
+    uint64_t TA[7];   // node types per level L (size 2^L), bit O for the node at
+    uint64_t TB[7];   // offset O: type = TA + 2 TB (0 mixed, 1 rate 0,
+                      // 2 rate 1, 3 repetition)
     uint32_t fv;      // lane i: SIGN if leaf i is frozen with value 1
     uint32_t w[7];    // lane i: SIGN if bit i of the frozen values re-encoded
                       // inside every aligned 2^t-block (w[0] = fv)
@@ -325,70 +329,201 @@ __device__ __forceinline__ void rep_node(float a, int O, Blk& B) {
     B.beta = sel_lanes(ones64(M) << O, B.w[ilog2<M>()] ^ (u ? SIGN : 0u), B.beta);
 }
 
+// ---------------------------------------------------------------------------
+// Small nodes with a known frozen pattern.  Moving a 1 of a channel index to
+// a less significant place, or dropping it, never lowers the Bhattacharyya
+// parameter, so in a code built from those parameters the frozen pattern of
+// every aligned node is closed under that order: an 8-leaf node has one of
+// only ten patterns.  Such a node is decoded by straight-line code generated
+// for its pattern at compile time (no per-node type tests, no loop); any
+// other pattern takes the generic path below.  The partial sums of these
+// nodes are carried as node-local bit words (bit j = element O + j).
+// ---------------------------------------------------------------------------
+constexpr int SPEC_M = 8;
+
+template <int M>
+constexpr uint32_t ones32() { return M >= 32 ? ~0u : (1u << M) - 1u; }
+
+// x G_M on node-local bits (G_M = F^{(x)m}, natural order)
+template <int M>
+__device__ __forceinline__ uint32_t enc_bits(uint32_t x) {
+#pragma unroll
+    for (int h = 1; h < M; h *= 2) x ^= (x >> h) & (uint32_t)low_mask64(h);
+    return x;
+}
+
+// Rate-1 node under min-sum: partial sums from the sign (S) and exact-zero
+// (Z) words of its LLRs by the three-state recursion
+//   left:  S_L = S_lo ^ S_hi,  Z_L = Z_lo | Z_hi
+//   right: Z_R = Z_lo & Z_hi,  S_R = Z_hi ? (S_lo ^ beta_L) : S_hi
+//   beta = [beta_L ^ beta_R, beta_R];  no zeros: beta = S
+// (hard decisions alone are not SC once an LLR is exactly zero).
+template <int M>
+__device__ __forceinline__ uint32_t r1_bits(uint32_t S, uint32_t Z) {
+    if constexpr (M == 1) {
+        return S & ~Z & 1u;
+    } else {
+        if (Z == 0) return S;
+        constexpr int H = M / 2;
+        constexpr uint32_t LO = ones32<H>();
+        const uint32_t bl = r1_bits<H>((S ^ (S >> H)) & LO, (Z | (Z >> H)) & LO);
+        const uint32_t zhi = Z >> H, shi = S >> H;
+        const uint32_t zr = Z & zhi & LO;
+        const uint32_t sr = ((zhi & (S ^ bl)) | (~zhi & shi)) & LO;
+        const uint32_t br = r1_bits<H>(sr, zr);
+        return (bl ^ br) | (br << H);
+    }
+}
+
+// Node of size M at lane offset O with frozen pattern P (bit j = leaf j
+// frozen) and frozen values fv (node-local bits); returns its partial sums.
+template <int M, uint32_t P, int FK, bool DUMP>
+__device__ __forceinline__ uint32_t sl_node(float a, int O, uint32_t fv, Blk& B) {
+    constexpr uint32_t ALL = ones32<M>();
+    if constexpr (P == ALL) {
+        return enc_bits<M>(fv);  // rate 0
+    } else if constexpr (M == 1) {
+        if (DUMP && lane_id() == O) {
+            B.leaf = a;
+            B.has_leaf = true;
+        }
+        return (uint32_t)(ballot(a < 0.0f) >> O) & 1u;
+    } else if constexpr (P == 0 && FK == 0) {
+        const uint32_t S = (uint32_t)(ballot(a < 0.0f) >> O) & ALL;
+        const uint32_t Z = (uint32_t)(ballot(a == 0.0f) >> O) & ALL;
+        return r1_bits<M>(S, Z);
+    } else if constexpr (P == (ALL >> 1)) {
+        const float last = rep_chain<M / 2, M>(a, B);  // repetition
+        const int il = O + M - 1;
+        if (DUMP && lane_id() == il) {
+            B.leaf = last;
+            B.has_leaf = true;
+        }
+        const uint32_t u = (uint32_t)(ballot(last < 0.0f) >> il) & 1u;
+        return enc_bits<M>(fv) ^ ((0u - u) & ALL);
+    } else {
+        constexpr int H = M / 2;
+        constexpr uint32_t LO = ones32<H>();
+        const float c = fupd<FK>(a, lane_downf<H>(a));
+        const uint32_t bl = sl_node<H, (P & LO), FK, DUMP>(c, O, fv & LO, B);
+        const uint32_t sg = lane_bit((uint64_t)bl << O) ? SIGN : 0u;
+        const float d = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ sg));
+        const uint32_t br = sl_node<H, (P >> H), FK, DUMP>(d, O + H, fv >> H, B);
+        return (bl ^ br) | (br << H);
+    }
+}
+
+template <int M, int FK, bool PRUNE, bool DUMP>
+__device__ __forceinline__ void blk_generic(float a, int O, Blk& B);
+
+// Size-SPEC_M node: straight-line code for the ten closed patterns.
+template <int FK, bool DUMP>
+__device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
+    constexpr int M = SPEC_M;
+    const uint32_t p = (uint32_t)(B.F >> O) & ones32<M>();
+    const uint32_t fv = (uint32_t)(B.V >> O) & ones32<M>();
+    uint32_t bits;
+    switch (p) {
+        case 0x00: bits = sl_node<M, 0x00, FK, DUMP>(a, O, fv, B); break;
+        case 0x01: bits = sl_node<M, 0x01, FK, DUMP>(a, O, fv, B); break;
+        case 0x03: bits = sl_node<M, 0x03, FK, DUMP>(a, O, fv, B); break;
+        case 0x07: bits = sl_node<M, 0x07, FK, DUMP>(a, O, fv, B); break;
+        case 0x0f: bits = sl_node<M, 0x0f, FK, DUMP>(a, O, fv, B); break;
+        case 0x17: bits = sl_node<M, 0x17, FK, DUMP>(a, O, fv, B); break;
+        case 0x1f: bits = sl_node<M, 0x1f, FK, DUMP>(a, O, fv, B); break;
+        case 0x3f: bits = sl_node<M, 0x3f, FK, DUMP>(a, O, fv, B); break;
+        case 0x7f: bits = sl_node<M, 0x7f, FK, DUMP>(a, O, fv, B); break;
+        case 0xff: bits = sl_node<M, 0xff, FK, DUMP>(a, O, fv, B); break;
+        default:
+            blk_generic<M, FK, true, DUMP>(a, O, B);
+            bits = (uint32_t)(ballot(B.beta != 0u) >> O) & ones32<M>();
+            break;
+    }
+    B.beta = sel_lanes(ones64(M) << O, lane_bit((uint64_t)bits << O) ? SIGN : 0u, B.beta);
+}
+
 // Node of size M at lane offset O (runtime).  Each size has one copy of its
 // code: the two children are visited by a two-pass loop that is kept rolled,
 // so the code grows with log M rather than with the number of nodes.
+//
+// Both ballots of a node are taken unconditionally at its top and only read
+// inside the shortcut branches: with a ballot placed under the rate-1 test
+// (or an early return nested in that test) this toolchain's -O2/-O3 code
+// returned corrupted partial sums after a failed test, exact at -O1.
 template <int M, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void blk_node(float a, int O, Blk& B) {
-    const uint64_t nm = ones64(M) << O;
+    if constexpr (PRUNE && M == SPEC_M) {
+        blk_spec<FK, DUMP>(a, O, B);
+    } else {
+        blk_generic<M, FK, PRUNE, DUMP>(a, O, B);
+    }
+}
+
+template <int M, int FK, bool PRUNE, bool DUMP>
+__device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
     if constexpr (M == 1) {
         if (DUMP && lane_id() == O) {
             B.leaf = a;
             B.has_leaf = true;
         }
-        // frozen: the revealed value; information bit: [alpha < 0]
-        const bool frozen = (B.F >> O) & 1ull;
-        const uint32_t d = frozen ? B.fv : ((a < 0.0f) ? SIGN : 0u);
-        B.beta = sel_lanes(nm, d, B.beta);
+        // frozen: the revealed value; information bit: [alpha < 0].  Lane O
+        // reads its own frozen bit, so the choice is a lane select.
+        const uint32_t d = lane_bit(B.F) ? B.fv : ((a < 0.0f) ? SIGN : 0u);
+        B.beta = sel_lanes(1ull << O, d, B.beta);
     } else {
+        constexpr int LG = ilog2<M>();
+        int type = 0;
+        uint64_t neg = 0, low = 0;
         if constexpr (PRUNE) {
-            const uint64_t fm = B.F & nm;
-            const bool rate0 = fm == nm;
-            const bool repn = fm == (nm ^ (1ull << (O + M - 1)));
-            // The rate-1 ballot is taken unconditionally and every shortcut
-            // leaves through one exit.  With the ballot under "if (rate 1)",
-            // or an early return nested in that test, this toolchain's -O2/-O3
-            // code returned corrupted partial sums after a failed rate-1 test
-            // (exact at -O1; found by the box-plus parity tests).
-            const uint64_t low = ballot(below_rate1_floor<FK, ilog2<M>()>(a)) & nm;
-            const bool rate1 = (fm == 0) & (low == 0);
-            if (rate0 | rate1 | repn) {
-                if (repn) {
-                    rep_node<M, DUMP>(a, O, B);
-                } else if (rate0) {
-                    B.beta = sel_lanes(nm, B.w[ilog2<M>()], B.beta);
-                } else {
-                    B.beta = sel_lanes(nm, (a < 0.0f) ? SIGN : 0u, B.beta);
-                }
-                return;
-            }
+            neg = ballot(a < 0.0f);
+            low = ballot(below_rate1_floor<FK, LG>(a));
+            type = (int)((B.TA[LG] >> O) & 1ull) | ((int)((B.TB[LG] >> O) & 1ull) << 1);
+            // rate-1 node with an LLR at or under the floor (an exact zero
+            // under min-sum): hard decisions need not be SC there, decode it
+            if (type == 2 && (low & (ones64(M) << O)) != 0) type = 0;
         }
-        constexpr int H = M / 2;
+        if (type == 0) {
+            constexpr int H = M / 2;
 #pragma clang loop unroll(disable)
-        for (int side = 0; side < 2; ++side) {
-            float c;
-            if (side == 0) {
-                c = fupd<FK>(a, lane_downf<H>(a));  // left child, lanes [O, O + H)
-            } else {
-                c = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ B.beta));  // right child
+            for (int side = 0; side < 2; ++side) {
+                float c;
+                if (side == 0) {
+                    c = fupd<FK>(a, lane_downf<H>(a));  // left child, lanes [O, O + H)
+                } else {
+                    c = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ B.beta));  // right child
+                }
+                blk_node<H, FK, PRUNE, DUMP>(c, O + side * H, B);
             }
-            blk_node<H, FK, PRUNE, DUMP>(c, O + side * H, B);
+            B.beta = sel_lanes(ones64(H) << O, B.beta ^ lane_down<H>(B.beta), B.beta);
+        } else if (type == 1) {
+            B.beta = sel_lanes(ones64(M) << O, B.w[LG], B.beta);
+        } else if (type == 3) {
+            rep_node<M, DUMP>(a, O, B);
+        } else {
+            B.beta = sel_lanes(ones64(M) << O, lane_bit(neg) ? SIGN : 0u, B.beta);
         }
-        B.beta = sel_lanes(ones64(H) << O, B.beta ^ lane_down<H>(B.beta), B.beta);
     }
 }
 
 // Block set-up from its frozen mask F and frozen values V (wave-uniform).
 __device__ __forceinline__ void blk_init(Blk& B, uint64_t F, uint64_t V) {
     B.F = F;
+    B.V = V & F;
     uint64_t W = V & F;
     B.w[0] = lane_bit(W) ? SIGN : 0u;
+    uint64_t r0 = F, r1 = ~F, rp = ~F;  // size 1: rate 0 = frozen, rate 1 = repetition = information
 #pragma unroll
     for (int t = 1; t < 7; ++t) {
         const int h = 1 << (t - 1);
         W ^= (W >> h) & low_mask64(h);
         B.w[t] = lane_bit(W) ? SIGN : 0u;
+        rp = r0 & (rp >> h);  // left half rate 0, right half repetition
+        r0 = r0 & (r0 >> h);
+        r1 = r1 & (r1 >> h);
+        B.TA[t] = r0 | rp;
+        B.TB[t] = r1 | rp;
     }
+    B.TA[0] = B.TB[0] = 0;
     B.fv = B.w[0];
     B.beta = 0;
     B.leaf = 0.0f;
