@@ -339,7 +339,11 @@ __device__ __forceinline__ void rep_node(float a, int O, Blk& B) {
 // other pattern takes the generic path below.  The partial sums of these
 // nodes are carried as node-local bit words (bit j = element O + j).
 // ---------------------------------------------------------------------------
-constexpr int SPEC_M = 8;
+#ifndef POLAR_SPEC_M
+#define POLAR_SPEC_M 16
+#endif
+constexpr int SPEC_M = POLAR_SPEC_M;
+static_assert(SPEC_M == 8 || SPEC_M == 16, "specialized node size");
 
 template <int M>
 constexpr uint32_t ones32() { return M >= 32 ? ~0u : (1u << M) - 1u; }
@@ -416,28 +420,65 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, uint32_t fv, Blk& B)
 template <int M, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void blk_generic(float a, int O, Blk& B);
 
-// Size-SPEC_M node: straight-line code for the ten closed patterns.
+// Size-SPEC_M node: straight-line code for each closed pattern (10 of 8
+// leaves, 27 of 16 leaves).
 template <int FK, bool DUMP>
 __device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
     constexpr int M = SPEC_M;
     const uint32_t p = (uint32_t)(B.F >> O) & ones32<M>();
     const uint32_t fv = (uint32_t)(B.V >> O) & ones32<M>();
     uint32_t bits;
-    switch (p) {
-        case 0x00: bits = sl_node<M, 0x00, FK, DUMP>(a, O, fv, B); break;
-        case 0x01: bits = sl_node<M, 0x01, FK, DUMP>(a, O, fv, B); break;
-        case 0x03: bits = sl_node<M, 0x03, FK, DUMP>(a, O, fv, B); break;
-        case 0x07: bits = sl_node<M, 0x07, FK, DUMP>(a, O, fv, B); break;
-        case 0x0f: bits = sl_node<M, 0x0f, FK, DUMP>(a, O, fv, B); break;
-        case 0x17: bits = sl_node<M, 0x17, FK, DUMP>(a, O, fv, B); break;
-        case 0x1f: bits = sl_node<M, 0x1f, FK, DUMP>(a, O, fv, B); break;
-        case 0x3f: bits = sl_node<M, 0x3f, FK, DUMP>(a, O, fv, B); break;
-        case 0x7f: bits = sl_node<M, 0x7f, FK, DUMP>(a, O, fv, B); break;
-        case 0xff: bits = sl_node<M, 0xff, FK, DUMP>(a, O, fv, B); break;
-        default:
-            blk_generic<M, FK, true, DUMP>(a, O, B);
-            bits = (uint32_t)(ballot(B.beta != 0u) >> O) & ones32<M>();
-            break;
+    if constexpr (M == 16) {
+        switch (p) {
+            case 0x0: bits = sl_node<M, 0x0, FK, DUMP>(a, O, fv, B); break;
+            case 0x1: bits = sl_node<M, 0x1, FK, DUMP>(a, O, fv, B); break;
+            case 0x3: bits = sl_node<M, 0x3, FK, DUMP>(a, O, fv, B); break;
+            case 0x7: bits = sl_node<M, 0x7, FK, DUMP>(a, O, fv, B); break;
+            case 0xf: bits = sl_node<M, 0xf, FK, DUMP>(a, O, fv, B); break;
+            case 0x17: bits = sl_node<M, 0x17, FK, DUMP>(a, O, fv, B); break;
+            case 0x1f: bits = sl_node<M, 0x1f, FK, DUMP>(a, O, fv, B); break;
+            case 0x3f: bits = sl_node<M, 0x3f, FK, DUMP>(a, O, fv, B); break;
+            case 0x7f: bits = sl_node<M, 0x7f, FK, DUMP>(a, O, fv, B); break;
+            case 0xff: bits = sl_node<M, 0xff, FK, DUMP>(a, O, fv, B); break;
+            case 0x117: bits = sl_node<M, 0x117, FK, DUMP>(a, O, fv, B); break;
+            case 0x11f: bits = sl_node<M, 0x11f, FK, DUMP>(a, O, fv, B); break;
+            case 0x13f: bits = sl_node<M, 0x13f, FK, DUMP>(a, O, fv, B); break;
+            case 0x17f: bits = sl_node<M, 0x17f, FK, DUMP>(a, O, fv, B); break;
+            case 0x1ff: bits = sl_node<M, 0x1ff, FK, DUMP>(a, O, fv, B); break;
+            case 0x33f: bits = sl_node<M, 0x33f, FK, DUMP>(a, O, fv, B); break;
+            case 0x37f: bits = sl_node<M, 0x37f, FK, DUMP>(a, O, fv, B); break;
+            case 0x3ff: bits = sl_node<M, 0x3ff, FK, DUMP>(a, O, fv, B); break;
+            case 0x77f: bits = sl_node<M, 0x77f, FK, DUMP>(a, O, fv, B); break;
+            case 0x7ff: bits = sl_node<M, 0x7ff, FK, DUMP>(a, O, fv, B); break;
+            case 0xfff: bits = sl_node<M, 0xfff, FK, DUMP>(a, O, fv, B); break;
+            case 0x177f: bits = sl_node<M, 0x177f, FK, DUMP>(a, O, fv, B); break;
+            case 0x17ff: bits = sl_node<M, 0x17ff, FK, DUMP>(a, O, fv, B); break;
+            case 0x1fff: bits = sl_node<M, 0x1fff, FK, DUMP>(a, O, fv, B); break;
+            case 0x3fff: bits = sl_node<M, 0x3fff, FK, DUMP>(a, O, fv, B); break;
+            case 0x7fff: bits = sl_node<M, 0x7fff, FK, DUMP>(a, O, fv, B); break;
+            case 0xffff: bits = sl_node<M, 0xffff, FK, DUMP>(a, O, fv, B); break;
+            default:
+                blk_generic<M, FK, true, DUMP>(a, O, B);
+                bits = (uint32_t)(ballot(B.beta != 0u) >> O) & ones32<M>();
+                break;
+        }
+    } else {
+        switch (p) {
+            case 0x0: bits = sl_node<M, 0x0, FK, DUMP>(a, O, fv, B); break;
+            case 0x1: bits = sl_node<M, 0x1, FK, DUMP>(a, O, fv, B); break;
+            case 0x3: bits = sl_node<M, 0x3, FK, DUMP>(a, O, fv, B); break;
+            case 0x7: bits = sl_node<M, 0x7, FK, DUMP>(a, O, fv, B); break;
+            case 0xf: bits = sl_node<M, 0xf, FK, DUMP>(a, O, fv, B); break;
+            case 0x17: bits = sl_node<M, 0x17, FK, DUMP>(a, O, fv, B); break;
+            case 0x1f: bits = sl_node<M, 0x1f, FK, DUMP>(a, O, fv, B); break;
+            case 0x3f: bits = sl_node<M, 0x3f, FK, DUMP>(a, O, fv, B); break;
+            case 0x7f: bits = sl_node<M, 0x7f, FK, DUMP>(a, O, fv, B); break;
+            case 0xff: bits = sl_node<M, 0xff, FK, DUMP>(a, O, fv, B); break;
+            default:
+                blk_generic<M, FK, true, DUMP>(a, O, B);
+                bits = (uint32_t)(ballot(B.beta != 0u) >> O) & ones32<M>();
+                break;
+        }
     }
     B.beta = sel_lanes(ones64(M) << O, lane_bit((uint64_t)bits << O) ? SIGN : 0u, B.beta);
 }

@@ -166,3 +166,72 @@ def test_repetition_node_shortcut(m):
         got_beta, last = rep_node_model(llr, fval)
         assert got_beta == _to_word(beta)
         assert np.float32(last).view(np.uint32) == leaf[-1].view(np.uint32)
+
+
+# ---------------------------------------------------------------------------
+# Straight-line small-node decoders: the kernel compiles one per frozen
+# pattern of an aligned 8- or 16-leaf node that is closed under the order of
+# the synthetic channels.  Check that its case list is exactly that closed
+# family, and that every aligned node of Bhattacharyya-built codes has one.
+# ---------------------------------------------------------------------------
+import os
+import re
+
+import synth
+
+SRC = os.path.join(os.path.dirname(__file__), "..", "paper_1204_5882_amd", "csrc", "sc_device.hip")
+
+
+def _weaker(j, m):
+    """Indices whose Bhattacharyya parameter is at least Z_j by one step:
+    drop a 1 of j, or move a 1 one place towards the least significant bit."""
+    out = []
+    for b in range(m):
+        if (j >> b) & 1:
+            out.append(j & ~(1 << b))
+            if b > 0 and not (j >> (b - 1)) & 1:
+                out.append((j & ~(1 << b)) | (1 << (b - 1)))
+    return out
+
+
+def closed_patterns(m):
+    size = 1 << m
+    res = []
+    for F in range(1 << size):
+        if all((F >> i) & 1 for j in range(size) if (F >> j) & 1 for i in _weaker(j, m)):
+            res.append(F)
+    return res
+
+
+def _kernel_cases():
+    src = open(SRC).read()
+    body = src[src.index("__device__ __forceinline__ void blk_spec"):]
+    body = body[: body.index("\n}\n")]
+    m16, m8 = body.split("} else {", 1)
+    grab = lambda t: sorted(int(x, 16) for x in re.findall(r"case (0x[0-9a-f]+):", t))
+    return {3: grab(m8), 4: grab(m16)}
+
+
+def test_closed_pattern_counts():
+    # 3 patterns of 2 leaves (FF, FI, II), 5 of 4, 10 of 8, 27 of 16
+    assert [len(closed_patterns(m)) for m in (1, 2, 3, 4)] == [3, 5, 10, 27]
+
+
+@pytest.mark.parametrize("m", [3, 4])
+def test_kernel_specializes_exactly_the_closed_patterns(m):
+    assert _kernel_cases()[m] == closed_patterns(m)
+
+
+@pytest.mark.parametrize("log2n,z0,n_frozen", [
+    (12, synth.bsc_z0(0.02), 819),
+    (16, synth.bsc_z0(0.05), -1),
+    (20, synth.bsc_z0(0.03), 262144),
+    (18, synth.biawgn_z0(0.97), -1),
+])
+def test_every_aligned_node_of_real_codes_is_closed(log2n, z0, n_frozen):
+    mask, _, _ = oracle.frozen_set(log2n, z0, n_frozen)
+    for m in (3, 4):
+        closed = set(closed_patterns(m))
+        rows = mask.reshape(-1, 1 << m).astype(np.uint64)
+        pats = (rows << np.arange(1 << m, dtype=np.uint64)).sum(axis=1)
+        assert set(int(p) for p in np.unique(pats)) <= closed
