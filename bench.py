@@ -11,7 +11,16 @@ on a sample of the frames, and the CPU oracle on a bounded sample.
 
 Inputs are synthetic and seeded (numpy Philox): u is uniform, x = u G_N is
 computed by libpolar's encoder, the channel noise is drawn per frame, and the
-frozen values are u on the frozen set.
+frozen values are u on the frozen set.  The CPU leg rebuilds its sample of
+frames from the same seeds with the oracle's own frozen set and encoder, and
+checks that they equal the GPU inputs before timing the oracle on them.
+
+The serving leg (on by default, --no-serve to skip) streams requests of
+N = 2^16 / 2^20 / 2^22 (probabilities 0.5 / 0.35 / 0.15; half BSC p = 0.03
+at rate 0.75, half BIAWGN sigma = 0.97 at rate 0.45, six frozen sets,
+min-sum) through polar_serve_*: first all at once to find the saturation
+throughput, then with Poisson arrivals at a fraction of it, reporting p50 /
+p99 latency from submit to completion.
 """
 from __future__ import annotations
 
@@ -78,11 +87,16 @@ def z0_of(channel, param):
     return synth.bsc_z0(param) if channel == "bsc" else synth.biawgn_z0(param)
 
 
+def frame_specs(cfg_name):
+    cfg = CONFIGS[cfg_name]
+    return cfg["frames"] if cfg["frames"] is not None else mixed_frames()
+
+
 def make_inputs(cfg_name, lp, torch, dev):
     """Returns (items, host_frames) with items ready for the binding and
     host_frames = list of (llr, mask bits, fval bits) kept for the CPU leg."""
     cfg = CONFIGS[cfg_name]
-    spec = cfg["frames"] if cfg["frames"] is not None else mixed_frames()
+    spec = frame_specs(cfg_name)
     masks = {}
     items, host = [], []
     for k, (log2n, ch, prm, nf) in enumerate(spec):
@@ -93,22 +107,17 @@ def make_inputs(cfg_name, lp, torch, dev):
                           torch.from_numpy(words.view(np.int32).copy()).to(dev))
         words, mbits, mdev = masks[key]
         n = 1 << log2n
-        g = synth.rng(cfg["seed_base"] + k)
-        u = synth.draw_bits(g, n)
-        udev = torch.from_numpy(synth.pack_bits(u).view(np.int32).copy()).to(dev)
-        xdev = lp.encode(log2n, udev)
-        torch.cuda.synchronize()
-        x = synth.unpack_bits(xdev.cpu().numpy().view(np.uint32), n)
-        if ch == "bsc":
-            llr = synth.bsc_llr(x ^ synth.bsc_noise(g, n, prm), prm)
-        else:
-            llr = synth.biawgn_llr(x, synth.gauss_noise(g, n), prm)
-        fval = (u & mbits).astype(np.uint8)
+
+        def gpu_encode(u, log2n=log2n, n=n):
+            x = lp.encode(log2n, torch.from_numpy(synth.pack_bits(u).view(np.int32).copy()).to(dev))
+            return synth.unpack_bits(x.cpu().numpy().view(np.uint32), n)
+
+        u, fval, llr = synth.frame(cfg["seed_base"] + k, log2n, ch, prm, mbits, gpu_encode)
         items.append(dict(log2n=log2n, f_kind=cfg["fkind"], llr=torch.from_numpy(llr).to(dev),
                           frozen_mask=mdev,
                           frozen_vals=torch.from_numpy(synth.pack_bits(fval).view(np.int32).copy()).to(dev),
                           u_hat=torch.zeros(lp.n_words(log2n), dtype=torch.int32, device=dev)))
-        host.append((llr, mbits, fval, u))
+        host.append((llr, mbits, fval))
     return items, host
 
 
@@ -140,19 +149,42 @@ def host_threads() -> int:
     return max(1, min(n, 16))
 
 
-def cpu_baseline(host, boxplus, budget_s=20.0):
+def oracle_frames(cfg_name, count):
+    """The first count frames of a workload rebuilt from their seeds with the
+    oracle's frozen set and encoder (no GPU code involved)."""
+    import oracle
+
+    cfg = CONFIGS[cfg_name]
+    spec = frame_specs(cfg_name)[:count]
+    masks, out = {}, []
+    for k, (log2n, ch, prm, nf) in enumerate(spec):
+        key = (log2n, ch, round(prm, 12), nf)
+        if key not in masks:
+            masks[key] = oracle.frozen_set(log2n, z0_of(ch, prm), nf, 0.1)[0]
+        mask = masks[key]
+        _, fval, llr = synth.frame(cfg["seed_base"] + k, log2n, ch, prm, mask, lambda v, n=log2n: oracle.encode(n, v))
+        out.append((llr, mask, fval))
+    return out
+
+
+def cpu_baseline(cfg_name, host, boxplus, budget_s=20.0):
     """The oracle as it is, on a bounded sample of the same frames (about
-    budget_s of CPU work), one frame per host thread."""
+    budget_s of CPU work), one frame per host thread.  Returns the baseline,
+    the oracle's u-hat of the sample, and whether the oracle-built inputs
+    equal the ones the GPU decoded."""
     import oracle
 
     threads = host_threads()
-    n = host[0][0].size
-    same = all(h[0].size == n for h in host)
+    first = oracle_frames(cfg_name, 1)
     t0 = time.perf_counter()
-    oracle.sc_decode(host[0][0], host[0][1], host[0][2], boxplus=boxplus)
+    oracle.sc_decode(first[0][0], first[0][1], first[0][2], boxplus=boxplus)
     one = max(time.perf_counter() - t0, 1e-4)
     count = max(1, min(len(host), int(budget_s / one)))
-    sample = host[:count]
+    sample = oracle_frames(cfg_name, count)
+    same_inputs = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+                      for a, b in zip(sample, host))
+    n = sample[0][0].size
+    same = all(h[0].size == n for h in sample)
     t0 = time.perf_counter()
     if same:
         llr = np.stack([h[0] for h in sample])
@@ -167,7 +199,89 @@ def cpu_baseline(host, boxplus, budget_s=20.0):
     bits = sum(h[0].size for h in sample)
     return dict(value=round(bits / wall / 1e6, 2), unit="Mbit/s", cores=threads, kind="oracle",
                 sample=f"first {count} of {len(host)} frames, {threads} host threads, {wall:.2f} s wall, "
-                       f"{one * count:.1f} s of single-thread work"), outs
+                       f"{one * count:.1f} s of single-thread work"), outs, same_inputs
+
+
+# ---------------------------------------------------------------- serving leg
+SERVE_MIX = [  # (log2n, probability)
+    (16, 0.50), (20, 0.35), (22, 0.15)]
+SERVE_CODES = [("bsc", 0.03, 0.75), ("biawgn", 0.97, 0.45)]
+
+
+def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, load=0.8, seed=50000):
+    """Requests drawn from a pool of resident frames (pool_per_size distinct
+    frames per (N, code)); each request writes its own u-hat buffer."""
+    g = np.random.default_rng(seed)
+    pool = {}
+    for log2n, _ in SERVE_MIX:
+        for ci, (ch, prm, rate) in enumerate(SERVE_CODES):
+            n = 1 << log2n
+            nf = n - int(rate * n)
+            words, _, _ = lp.build_frozen_set(log2n, z0_of(ch, prm), nf, 0.1)
+            mbits = synth.unpack_bits(words, n)
+            mdev = torch.from_numpy(words.view(np.int32).copy()).to(dev)
+            frames = []
+            for j in range(pool_per_size):
+                def gpu_encode(u, log2n=log2n, n=n):
+                    x = lp.encode(log2n, torch.from_numpy(synth.pack_bits(u).view(np.int32).copy()).to(dev))
+                    return synth.unpack_bits(x.cpu().numpy().view(np.uint32), n)
+
+                _, fval, llr = synth.frame(seed + 100 * log2n + 10 * ci + j, log2n, ch, prm, mbits, gpu_encode)
+                frames.append(dict(log2n=log2n, f_kind=0, llr=torch.from_numpy(llr).to(dev), frozen_mask=mdev,
+                                   frozen_vals=torch.from_numpy(synth.pack_bits(fval).view(np.int32).copy()).to(dev)))
+            pool[(log2n, ci)] = frames
+    sizes = [m[0] for m in SERVE_MIX]
+    probs = [m[1] for m in SERVE_MIX]
+    reqs = []
+    for r in range(n_requests):
+        log2n = int(g.choice(sizes, p=probs))
+        ci = int(g.integers(0, len(SERVE_CODES)))
+        src = pool[(log2n, ci)][int(g.integers(0, pool_per_size))]
+        it = dict(src)
+        it["u_hat"] = torch.zeros(lp.n_words(log2n), dtype=torch.int32, device=dev)
+        reqs.append(it)
+    bits = np.array([1 << it["log2n"] for it in reqs], np.float64)
+    ctx = lp.Ctx(0)
+    arena_bytes = 8 << 30
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        srv = lp.Server(ctx, arena, poll_us=0)
+        lat = np.zeros(len(reqs))
+        done = 0
+        nxt = 0
+        t0 = time.perf_counter()
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and arrivals[nxt] <= now:
+                srv.submit(reqs[nxt], nxt)
+                nxt += 1
+            for rid, st, l in srv.poll():
+                if st != lp.POLAR_OK:
+                    raise RuntimeError(f"request {rid} failed with {st}")
+                lat[rid] = l
+                done += 1
+        wall = time.perf_counter() - t0
+        srv.close()
+        return wall, lat
+
+    # saturation: everything queued at t = 0
+    run(np.zeros(len(reqs)))  # warm-up
+    wall_sat, _ = run(np.zeros(len(reqs)))
+    sat_mbit = bits.sum() / wall_sat / 1e6
+    rate = load * sat_mbit * 1e6 / bits.mean()  # requests per second
+    arrivals = np.cumsum(g.exponential(1.0 / rate, len(reqs)))
+    wall, lat = run(arrivals)
+    ctx.close()
+    return dict(requests=len(reqs), mix="N=2^16/2^20/2^22 at 0.5/0.35/0.15; BSC p=0.03 R=0.75 and BIAWGN "
+                "sigma=0.97 R=0.45 (min-sum), Poisson arrivals",
+                saturation_Mbit_s=round(sat_mbit, 1), load=load, arrival_rate_req_s=round(rate, 1),
+                Mbit_s=round(bits.sum() / wall / 1e6, 1),
+                p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
+                p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3),
+                mean_ms=round(float(lat.mean()) * 1e3, 3), arena_bytes=arena_bytes,
+                note="latency = host time from submit to the poll that sees the request's batch done")
 
 
 def main(argv=None):
@@ -181,6 +295,10 @@ def main(argv=None):
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--prune", type=int, default=1)
     ap.add_argument("--waves", type=int, default=0, help="wavefronts per workgroup (0 = library default)")
+    ap.add_argument("--cutover", type=int, default=0, help="register-resident subtree log2 (0 = library default)")
+    ap.add_argument("--graph", type=int, default=0, help="replay the batch through a HIP graph")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -205,6 +323,10 @@ def main(argv=None):
     ctx.set_option(lp.POLAR_OPT_PRUNE, args.prune)
     if args.waves:
         ctx.set_option(lp.POLAR_OPT_WG_WAVES, args.waves)
+    if args.cutover:
+        ctx.set_option(lp.POLAR_OPT_CUTOVER, args.cutover)
+    if args.graph:
+        ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
     frames = lp.make_frames(items)
     ctx.ensure_workspace(frames, n)
     torch.cuda.synchronize()
@@ -228,7 +350,8 @@ def main(argv=None):
                config=dict(workload=f"{args.config}: {cfg['desc']}", frames=n,
                            bits_per_step=total_bits, info_bits_per_step=info_bits,
                            f_kind="boxplus" if cfg["fkind"] else "minsum", prune=bool(args.prune),
-                           waves_per_workgroup=ctx.get_option(lp.POLAR_OPT_WG_WAVES)),
+                           graph=bool(args.graph),
+                           launch=ctx.query_launch(cfg["fkind"], max(it["log2n"] for it in items), n)),
                roofline=roof,
                kernel_ms_mean=round(ev_ms, 3), kernel_ms_min=round(float(np.min(per)), 3),
                info_Mbit_s=round(info_bits / (ms_step / 1e3) / 1e6, 1),
@@ -260,10 +383,15 @@ def main(argv=None):
                             note="one launch per frame, one workgroup, no pruning, serial on one stream")
         out["speedup_vs_plain"] = round(value / (pbits / pw / 1e6), 1)
 
+    if not args.no_serve:
+        print("[bench] serving leg", file=sys.stderr, flush=True)
+        out["serving"] = serve_leg(lp, torch, dev, n_requests=args.serve_requests)
+
     if not args.no_cpu:
         print("[bench] CPU oracle leg", file=sys.stderr, flush=True)
-        cb, outs = cpu_baseline(host, boxplus=bool(cfg["fkind"]))
+        cb, outs, same_inputs = cpu_baseline(args.config, host, boxplus=bool(cfg["fkind"]))
         out["cpu_baseline"] = cb
+        out["oracle_inputs_equal_gpu_inputs"] = same_inputs
         # the batched GPU output of the timed run, checked on the same sample
         ok = True
         for k, ref in enumerate(outs):

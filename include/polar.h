@@ -114,16 +114,26 @@ typedef struct polar_ctx polar_ctx;
 
 /* Options for polar_ctx_set_option. */
 #define POLAR_OPT_PRUNE 1       /* 0/1: exact rate-0 / rate-1 node shortcuts (default 1) */
-#define POLAR_OPT_CUTOVER 2     /* log2 of the register-resident subtree, 6..12;
-                                   0 = automatic (default)                               */
-#define POLAR_OPT_WG_WAVES 3    /* wavefronts per workgroup: 1, 2, 4, 8 or 16; 0 = auto */
-#define POLAR_OPT_MAX_SLOTS 4   /* max frames in flight (workgroups); 0 = auto          */
+#define POLAR_OPT_CUTOVER 2     /* log2 of the subtree decoded by one wavefront from
+                                   LDS / registers (larger nodes stream through HBM):
+                                   10, 11 or 12; 0 = automatic (default: the tuned
+                                   value, else 12).  Leaf-LLR dumps and unpruned
+                                   decoding always use 12.                                */
+#define POLAR_OPT_WG_WAVES 3    /* wavefronts per workgroup: 4 or 8; 0 = automatic.
+                                   Pruned box-plus decoding runs with at most 4.        */
+#define POLAR_OPT_MAX_SLOTS 4   /* max frames in flight (workgroups); 0 = automatic
+                                   (the tuned value, else 2 per compute unit)           */
 #define POLAR_OPT_TIMING 5      /* device pointer (as an integer) to 8 zeroed uint64
                                    counters, or 0 = off.  Decoding then adds, per frame:
                                    [0] ticks spent in register-resident subtree decoding
                                    (the serial leaf region), [1] ticks for the whole
                                    frame, [2] 1.  Ticks are the 100 MHz s_memrealtime
                                    clock, summed over frames in flight.              */
+#define POLAR_OPT_GRAPH 6       /* 0/1: polar_sc_decode_batch replays each distinct batch
+                                   (same descriptors, options and workspace) through a
+                                   cached HIP graph [descriptor copy, counter reset,
+                                   decode].  The host descriptor array is still read at
+                                   every call; up to 16 graphs are kept per context.    */
 
 /*
  * Create a decoding context on a device.  The context owns only host-side
@@ -166,6 +176,83 @@ int polar_sc_decode_batch(polar_ctx* ctx, const polar_frame* frames, int n_frame
  * serially on the stream.  Same arguments, workspace and results.
  */
 int polar_sc_decode_plain(polar_ctx* ctx, const polar_frame* frames, int n_frames, void* stream);
+
+/*
+ * Autotuner.  Times every built launch configuration (cutover 10..12,
+ * 4 or 8 wavefronts per workgroup, 1..3 frames in flight per compute unit)
+ * on these frames with the context's workspace (configurations that do not
+ * fit it are skipped), median of reps runs after one warm-up, and records
+ * the fastest for (f_kind, largest log2n of the frames).  Later batches whose
+ * largest frame has that size use it unless an option is set explicitly.
+ * Frames must share one f_kind, must not request leaf LLRs, and pruning must
+ * be on.  The frames' u_hat buffers are overwritten.  Outputs may be NULL.
+ */
+int polar_autotune(polar_ctx* ctx, const polar_frame* frames, int n_frames, int reps, void* stream,
+                   int* best_cutover, int* best_waves, int* best_slots, double* best_ms);
+
+/* Launch configuration a batch of n_frames frames of f_kind whose largest
+   frame has log2n would use under the context's options and tuned table. */
+int polar_query_launch(const polar_ctx* ctx, int f_kind, int log2n, int n_frames, int* cutover, int* waves,
+                       int* slots);
+
+/* Tuned table: forget it, or save / load it as JSON
+   {"libpolar_tune": 1, "entries": [{"f_kind", "log2n", "cutover", "waves", "slots"}, ...]}.
+   Loading merges into the table and rejects out-of-range entries. */
+int polar_tune_clear(polar_ctx* ctx);
+int polar_tune_save(const polar_ctx* ctx, const char* path);
+int polar_tune_load(polar_ctx* ctx, const char* path);
+
+/*
+ * Serving.  Requests (one frame each, caller-owned device buffers that must
+ * stay valid until the request completes) are queued, admitted against a
+ * caller-provided device arena and decoded in batches by the batch decoder on
+ * up to four internal streams at once: a new batch starts on an idle stream
+ * with the requests that have arrived, in arrival order, as many as fit the
+ * free arena (and at most max_slots), while earlier batches still run.  A
+ * batch needs the polar_workspace_bytes of its frames; a request too large
+ * for the whole arena completes with POLAR_E_NOMEM.  Results equal those of
+ * decoding the frame alone.  Latency is host time from submit to the poll
+ * that finds the request's batch finished.  A server is used from one host
+ * thread.
+ */
+typedef struct polar_serve_cfg {
+    size_t arena_bytes;  /* >= 4096                                             */
+    void* arena;         /* device, 256-byte aligned, caller-owned               */
+    int max_slots;       /* max requests per batch; 0 = 2 per compute unit       */
+    int poll_us;         /* idle sleep of polar_serve between polls (0 = spin)   */
+} polar_serve_cfg;
+
+typedef struct polar_completion {
+    uint64_t req_id;
+    int32_t status;      /* POLAR_OK, POLAR_E_NOMEM, POLAR_E_CANCELLED, POLAR_E_DEVICE */
+    int32_t reserved;
+    double latency_s;
+} polar_completion;
+
+typedef struct polar_server polar_server;
+
+int polar_serve_open(polar_ctx* ctx, const polar_serve_cfg* cfg, polar_server** out);
+/* Queue a request (copied).  POLAR_E_BUSY when 65536 requests are queued. */
+int polar_serve_submit(polar_server* srv, const polar_frame* req, uint64_t req_id);
+/* Reap finished batches, start new ones, and return up to max_out completions. */
+int polar_serve_poll(polar_server* srv, polar_completion* out, int max_out, int* n_out);
+/* Requests waiting, running, and completed but not yet returned by a poll. */
+int polar_serve_pending(const polar_server* srv, int* queued, int* running, int* completed);
+/* Cancel a queued request (it completes with POLAR_E_CANCELLED); POLAR_E_BUSY
+   if it is already running, POLAR_E_INVAL if unknown. */
+int polar_serve_cancel(polar_server* srv, uint64_t req_id);
+/* Wait for running batches and free the server; queued requests are dropped. */
+int polar_serve_close(polar_server* srv);
+
+/*
+ * Blocking loop over the calls above: next() is asked for requests until it
+ * returns 1 (none yet) or 2 (no more); done() is called once per request
+ * (also for requests refused at submit, with latency 0).  Returns when next()
+ * has returned 2 and every request has completed.
+ */
+typedef int (*polar_next_fn)(void* user, polar_frame* req, uint64_t* req_id); /* 0 ok, 1 none yet, 2 end */
+typedef void (*polar_done_fn)(void* user, uint64_t req_id, int status, double latency_s);
+int polar_serve(polar_ctx* ctx, const polar_serve_cfg* cfg, polar_next_fn next, polar_done_fn done, void* user);
 
 /*
  * Diagnostics: exercises the cross-lane moves (DPP row shifts, permlane

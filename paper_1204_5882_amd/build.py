@@ -2,12 +2,16 @@
 
     python -m paper_1204_5882_amd.build
 
-Each translation unit is compiled to an object in parallel, then linked into
-paper_1204_5882_amd/libpolar.so next to this file.
+Each translation unit (host code, common device code, and one unit per
+decoder variant under csrc/variants) is compiled to an object in parallel,
+then linked into paper_1204_5882_amd/libpolar.so next to this file.  The
+device assembly of every unit is kept in _build/ (for the ISA checks in the
+tests).
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
+import glob
 import os
 import subprocess
 import sys
@@ -34,7 +38,8 @@ COMMON = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["sc_device.hip", "polar_host.cpp"]
+SOURCES = ["sc_device.hip", "polar_host.cpp", "polar_tune.cpp", "polar_serve.cpp"] + sorted(
+    os.path.relpath(f, CSRC) for f in glob.glob(os.path.join(CSRC, "variants", "*.hip")))
 
 # Device code runs with the IEEE mode bit off: min/max then need no NaN
 # quieting, so the min-sum check update is one v_min_f32 with |.| modifiers.
@@ -42,30 +47,53 @@ SOURCES = ["sc_device.hip", "polar_host.cpp"]
 DEVICE_ONLY = ["-mno-amdgpu-ieee", "-fno-honor-nans"]
 
 
-ISA_OUT = os.path.join(BUILD_DIR, "sc_device-gfx950.s")
+LLVM_BIN = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin")
 
 
-def _compile(src: str) -> str:
-    if src == "@isa":
-        # device assembly of the kernels, kept for the ISA checks in the tests
-        cmd = [HIPCC, *COMMON, *DEVICE_ONLY, "--cuda-device-only", "-S", os.path.join(CSRC, "sc_device.hip"),
-               "-o", ISA_OUT]
-        out = ISA_OUT
-    else:
-        out = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-        extra = DEVICE_ONLY if src.endswith(".hip") else []
-        cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", out]
+def _run(cmd, what):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError(f"hipcc failed on {src}")
+        raise RuntimeError(f"{what} failed")
+    return r.stdout
+
+
+def _dump_isa(obj: str, name: str) -> None:
+    """Disassembly and kernel metadata of the gfx950 code object embedded in
+    obj, written to _build/<name>.gfx950.isa for the ISA checks."""
+    tool = lambda t: os.path.join(LLVM_BIN, t)
+    fatbin = os.path.join(BUILD_DIR, name + ".fatbin")
+    co = os.path.join(BUILD_DIR, name + ".gfx950.co")
+    _run([tool("llvm-objcopy"), "--dump-section", f".hip_fatbin={fatbin}", obj], f"fatbin of {name}")
+    _run([tool("clang-offload-bundler"), "--unbundle", "--type=o", f"--input={fatbin}",
+          f"--targets=hipv4-amdgcn-amd-amdhsa--{ARCH}", f"--output={co}"], f"unbundle {name}")
+    text = _run([tool("llvm-objdump"), "-d", f"--mcpu={ARCH}", co], f"disassemble {name}")
+    notes = _run([tool("llvm-readelf"), "--notes", co], f"notes of {name}")
+    with open(os.path.join(BUILD_DIR, name + f".{ARCH}.isa"), "w") as f:
+        f.write(notes)
+        f.write(text)
+
+
+def _compile(src: str) -> str:
+    name = os.path.splitext(os.path.basename(src))[0]
+    out = os.path.join(BUILD_DIR, name + ".o")
+    cmd = [HIPCC, *COMMON]
+    if src.endswith(".hip"):
+        cmd += DEVICE_ONLY
+    cmd += ["-c", os.path.join(CSRC, src), "-o", out]
+    _run(cmd, f"hipcc on {src}")
+    if src.endswith(".hip"):
+        _dump_isa(out, name)
     return out
 
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
-        objs = list(ex.map(_compile, SOURCES + ["@isa"]))[: len(SOURCES)]
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    # longest units first
+    order = sorted(SOURCES, key=lambda f: ("prune" not in f, not f.endswith(".hip")))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, order))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -14,9 +14,12 @@
 #include <string>
 #include <vector>
 
+#include "host_internal.h"
 #include "sc_device.h"
 
-namespace {
+using namespace polar_host;
+
+namespace polar_host {
 
 thread_local std::string g_err;
 
@@ -36,25 +39,23 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(POLAR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Keeps the caller's current device unchanged across a call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+}
 
-int64_t words_of(int log2n) { return log2n >= 5 ? ((int64_t)1 << (log2n - 5)) : 1; }
+DeviceGuard::~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+namespace {
+int64_t words_of(int log2n) { return log2n >= 5 ? ((int64_t)1 << (log2n - 5)) : 1; }
 }  // namespace
+
+}  // namespace polar_host
 
 // ---------------------------------------------------------------------------
 // Frozen set (Section 3): Bhattacharyya parameters of the synthetic channels,
@@ -132,7 +133,7 @@ extern "C" int polar_build_frozen_set(int log2n, double z0, int64_t n_frozen, do
     } else if (nf > 0 && nf < n) {
         std::nth_element(idx.begin(), idx.begin() + nf, idx.end(), less);
     }
-    const int64_t nw = words_of(log2n);
+    const int64_t nw = log2n >= 5 ? ((int64_t)1 << (log2n - 5)) : 1;
     std::memset(frozen_mask, 0, sizeof(uint32_t) * (size_t)nw);
     for (int64_t t = 0; t < nf; ++t) {
         const int64_t i = idx[(size_t)t];
@@ -156,40 +157,55 @@ extern "C" int polar_encode(int log2n, int n_frames, const uint32_t* u, uint32_t
 }
 
 // ---------------------------------------------------------------------------
-// Context.
+// Batches: plan, descriptor upload, launches, optional graph replay.
 // ---------------------------------------------------------------------------
-struct polar_ctx {
-    int device = 0;
-    int n_cu = 256;
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    int prune = 1;
-    int cutover = 0;    // 0 = automatic
-    int waves = 0;      // 0 = automatic
-    int max_slots = 0;  // 0 = automatic
-    unsigned long long* prof = nullptr;  // optional device timing counters
-    FrameDesc* staging = nullptr;  // pinned host copy of the descriptor table
-    size_t staging_cap = 0;
-    hipEvent_t staged = nullptr;   // recorded after the last descriptor upload
-    bool staged_pending = false;
-};
+namespace polar_host {
 
 namespace {
-
-int eff_cutover(const polar_ctx* c) { return c->cutover ? c->cutover : 12; }
-int eff_waves(const polar_ctx* c) { return c->waves ? c->waves : 4; }
-int eff_max_slots(const polar_ctx* c) { return c->max_slots ? c->max_slots : 2 * c->n_cu; }
-
 constexpr size_t kHeaderBytes = 256;  // work counters
+constexpr size_t kMaxGraphs = 16;
+}  // namespace
 
-struct Plan {
-    std::vector<FrameDesc> descs;  // sorted, grouped
-    struct Group { int fk, dump, first, count; };
-    std::vector<Group> groups;
-    int slots = 0;
-    int64_t slot_bytes = 0;
-    size_t desc_off = 0, slot_off = 0, total = 0;
-};
+int Stager::upload(const FrameDesc* d, size_t n, void* dst, hipStream_t s) {
+    if (n == 0) return ok();
+    if (!ev) {
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    if (pending) {
+        hipError_t e = hipEventSynchronize(ev);
+        if (e != hipSuccess) return hip_fail(e, "descriptor staging");
+        pending = false;
+    }
+    if (n > cap) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        const size_t want = std::max(n, (size_t)1024);
+        hipError_t e = hipHostMalloc((void**)&buf, want * sizeof(FrameDesc), hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "pinned descriptor buffer");
+        cap = want;
+    }
+    std::memcpy(buf, d, n * sizeof(FrameDesc));
+    hipError_t e = hipMemcpyAsync(dst, buf, n * sizeof(FrameDesc), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    e = hipEventRecord(ev, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload event");
+    pending = true;
+    return ok();
+}
+
+void Stager::release() {
+    if (ev) {
+        (void)hipEventSynchronize(ev);
+        (void)hipEventDestroy(ev);
+        ev = nullptr;
+    }
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    pending = false;
+}
 
 int validate_frames(const polar_frame* frames, int n_frames) {
     if (n_frames < 0) return fail(POLAR_E_INVAL, "n_frames < 0");
@@ -209,9 +225,27 @@ int validate_frames(const polar_frame* frames, int n_frames) {
     return ok();
 }
 
-// Layout of the workspace for a batch: [counters | descriptors | slots].
-void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool plain, Plan& p) {
-    const int cut = plain ? 12 : eff_cutover(c);
+LaunchCfg group_cfg(const polar_ctx* c, int fk, int maxlog, int count, bool dump, bool plain) {
+    LaunchCfg cfg;
+    if (plain) {
+        cfg.cutover = 12;
+        cfg.waves = 4;
+        cfg.slots = 1;
+        return cfg;
+    }
+    cfg.slots = 2 * c->n_cu;
+    auto it = c->tuned.find({fk, maxlog});
+    if (it != c->tuned.end()) cfg = it->second;
+    if (c->cutover) cfg.cutover = c->cutover;
+    if (c->waves) cfg.waves = c->waves;
+    if (c->max_slots) cfg.slots = c->max_slots;
+    if (dump || !c->prune) cfg.cutover = 12;
+    cfg.slots = std::max(1, std::min(cfg.slots, count));
+    return cfg;
+}
+
+void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool plain, Plan& p,
+               const LaunchCfg* force) {
     std::vector<int> order((size_t)n_frames);
     std::iota(order.begin(), order.end(), 0);
     // group by (f_kind, leaf dump); inside a group, most work first
@@ -222,7 +256,6 @@ void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool
     });
     p.descs.clear();
     p.groups.clear();
-    int maxlog = 0;
     for (int k = 0; k < n_frames; ++k) {
         const polar_frame& f = frames[order[(size_t)k]];
         FrameDesc d{};
@@ -234,74 +267,42 @@ void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool
         d.log2n = f.log2n;
         d.fkind = f.f_kind;
         p.descs.push_back(d);
-        maxlog = std::max(maxlog, (int)f.log2n);
         if (p.groups.empty() || key(order[(size_t)k]) != p.groups.back().fk * 2 + p.groups.back().dump)
-            p.groups.push_back({f.f_kind, f.leaf_llr ? 1 : 0, k, 0});
+            p.groups.push_back({f.f_kind, f.leaf_llr ? 1 : 0, k, 0, (int)f.log2n, LaunchCfg{}});
         p.groups.back().count++;
     }
-    int slots = 0;
-    for (auto& g : p.groups) slots = std::max(slots, plain ? 1 : std::min(g.count, eff_max_slots(c)));
-    p.slots = slots;
-    p.slot_bytes = n_frames ? polar_dev_slot_bytes(maxlog, cut) : 0;
+    p.slots = 0;
+    p.slot_bytes = 0;
+    for (auto& g : p.groups) {
+        g.cfg = group_cfg(c, g.fk, g.maxlog, g.count, g.dump != 0, plain);
+        if (force && !plain) {
+            g.cfg = *force;
+            if (g.dump || !c->prune) g.cfg.cutover = 12;
+            g.cfg.slots = std::max(1, std::min(g.cfg.slots, g.count));
+        }
+        p.slots = std::max(p.slots, g.cfg.slots);
+        p.slot_bytes = std::max(p.slot_bytes, polar_dev_slot_bytes(g.maxlog, g.cfg.cutover));
+    }
     p.desc_off = kHeaderBytes;
     p.slot_off = align256(p.desc_off + sizeof(FrameDesc) * (size_t)n_frames);
     p.total = p.slot_off + (size_t)p.slots * (size_t)p.slot_bytes;
 }
 
-int upload_descs(polar_ctx* c, const Plan& p, hipStream_t s) {
-    const size_t n = p.descs.size();
-    if (n == 0) return ok();
-    if (c->staged_pending) {
-        hipError_t e = hipEventSynchronize(c->staged);
-        if (e != hipSuccess) return hip_fail(e, "descriptor staging");
-        c->staged_pending = false;
-    }
-    if (n > c->staging_cap) {
-        if (c->staging) (void)hipHostFree(c->staging);
-        c->staging = nullptr;
-        size_t cap = std::max(n, (size_t)1024);
-        hipError_t e = hipHostMalloc((void**)&c->staging, cap * sizeof(FrameDesc), hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(e, "pinned descriptor buffer");
-        c->staging_cap = cap;
-    }
-    std::memcpy(c->staging, p.descs.data(), n * sizeof(FrameDesc));
-    hipError_t e = hipMemcpyAsync((uint8_t*)c->ws + p.desc_off, c->staging, n * sizeof(FrameDesc),
-                                  hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-    e = hipEventRecord(c->staged, s);
-    if (e != hipSuccess) return hip_fail(e, "descriptor upload event");
-    c->staged_pending = true;
-    return ok();
-}
+namespace {
 
-int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* stream, bool plain) {
-    if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
-    int rc = validate_frames(frames, n_frames);
-    if (rc) return rc;
-    if (n_frames == 0) return ok();
-    Plan p;
-    make_plan(c, frames, n_frames, plain, p);
-    if (!c->ws || c->ws_bytes < p.total)
-        return fail(POLAR_E_NOMEM, "workspace of %zu bytes < %zu required", c->ws_bytes, p.total);
-    DeviceGuard g(c->device);
-    if (!g.ok) return fail(POLAR_E_DEVICE, "cannot select device %d", c->device);
-    hipStream_t s = (hipStream_t)stream;
-    rc = upload_descs(c, p, s);
-    if (rc) return rc;
-    uint8_t* base = (uint8_t*)c->ws;
+int enqueue_launches(polar_ctx* c, const Plan& p, void* ws, hipStream_t s, bool plain) {
+    uint8_t* base = (uint8_t*)ws;
     unsigned* counter = (unsigned*)base;
     const FrameDesc* dtab = (const FrameDesc*)(base + p.desc_off);
     uint8_t* slots = base + p.slot_off;
-    const int cut = plain ? 12 : eff_cutover(c);
-    const int waves = plain ? 4 : eff_waves(c);
     const int prune = plain ? 0 : c->prune;
     for (const auto& gr : p.groups) {
         DecodeLaunch a{};
-        a.cutover = cut;
+        a.cutover = gr.cfg.cutover;
         a.fk = gr.fk;
         a.prune = prune;
         a.dump = gr.dump;
-        a.waves = waves;
+        a.waves = gr.cfg.waves;
         a.counter = counter;
         a.slots = slots;
         a.slot_bytes = p.slot_bytes;
@@ -318,7 +319,7 @@ int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* str
         } else {
             a.descs = dtab + gr.first;
             a.n_frames = gr.count;
-            a.grid = std::min(gr.count, eff_max_slots(c));
+            a.grid = gr.cfg.slots;
             hipError_t e = polar_dev_launch_decode(&a);
             if (e != hipSuccess) return hip_fail(e, "decode launch");
         }
@@ -326,7 +327,123 @@ int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* str
     return ok();
 }
 
+uint64_t fnv1a(const std::vector<uint8_t>& v) {
+    uint64_t h = 1469598103934665603ull;
+    for (uint8_t b : v) h = (h ^ b) * 1099511628211ull;
+    return h;
+}
+
+template <class T>
+void put(std::vector<uint8_t>& v, const T& x) {
+    const uint8_t* p = reinterpret_cast<const uint8_t*>(&x);
+    v.insert(v.end(), p, p + sizeof(T));
+}
+
+// Replays the batch through a cached graph: [descriptor copy, counter reset,
+// decode launch] per group, captured once for these exact descriptors,
+// launch parameters and workspace.
+int run_graph(polar_ctx* c, const Plan& p, void* ws, hipStream_t s) {
+    std::vector<uint8_t> key;
+    put(key, ws);
+    put(key, c->prof);
+    put(key, c->prune);
+    for (const auto& g : p.groups) {
+        put(key, g.first);
+        put(key, g.count);
+        put(key, g.cfg.cutover);
+        put(key, g.cfg.waves);
+        put(key, g.cfg.slots);
+    }
+    put(key, p.slot_bytes);
+    const uint8_t* d = reinterpret_cast<const uint8_t*>(p.descs.data());
+    key.insert(key.end(), d, d + p.descs.size() * sizeof(FrameDesc));
+    const uint64_t h = fnv1a(key);
+    auto it = c->graphs.find(h);
+    if (it != c->graphs.end() && it->second.key != key) {
+        // hash collision: drop the old entry
+        (void)hipGraphExecDestroy(it->second.exec);
+        (void)hipHostFree(it->second.pinned);
+        c->graphs.erase(it);
+        it = c->graphs.end();
+    }
+    if (it == c->graphs.end()) {
+        if (c->graphs.size() >= kMaxGraphs) {
+            auto victim = c->graphs.begin();
+            for (auto j = c->graphs.begin(); j != c->graphs.end(); ++j)
+                if (j->second.last_use < victim->second.last_use) victim = j;
+            // the victim may still be running on some stream
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "graph cache eviction");
+            (void)hipGraphExecDestroy(victim->second.exec);
+            (void)hipHostFree(victim->second.pinned);
+            c->graphs.erase(victim);
+        }
+        if (!c->capture_stream) {
+            hipError_t e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "capture stream");
+        }
+        GraphEntry ge;
+        ge.key = key;
+        const size_t nb = p.descs.size() * sizeof(FrameDesc);
+        hipError_t e = hipHostMalloc((void**)&ge.pinned, std::max(nb, (size_t)64), hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "pinned graph descriptors");
+        std::memcpy(ge.pinned, p.descs.data(), nb);
+        hipStream_t cs = c->capture_stream;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipHostFree(ge.pinned);
+            return hip_fail(e, "begin graph capture");
+        }
+        e = hipMemcpyAsync((uint8_t*)ws + p.desc_off, ge.pinned, nb, hipMemcpyHostToDevice, cs);
+        int rc = e == hipSuccess ? enqueue_launches(c, p, ws, cs, false) : hip_fail(e, "captured copy");
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (rc == POLAR_OK && e2 != hipSuccess) rc = hip_fail(e2, "end graph capture");
+        if (rc == POLAR_OK) {
+            e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = hip_fail(e, "graph instantiate");
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc != POLAR_OK) {
+            (void)hipHostFree(ge.pinned);
+            return rc;
+        }
+        it = c->graphs.emplace(h, std::move(ge)).first;
+    }
+    it->second.last_use = ++c->graph_clock;
+    hipError_t e = hipGraphLaunch(it->second.exec, s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return ok();
+}
+
 }  // namespace
+
+int run_plan(polar_ctx* c, const Plan& p, void* ws, size_t ws_bytes, hipStream_t s, Stager& st, bool plain) {
+    if (!ws || ws_bytes < p.total)
+        return fail(POLAR_E_NOMEM, "workspace of %zu bytes < %zu required", ws ? ws_bytes : (size_t)0, p.total);
+    if (((uintptr_t)ws & 255) != 0) return fail(POLAR_E_INVAL, "workspace must be 256-byte aligned");
+    int rc = st.upload(p.descs.data(), p.descs.size(), (uint8_t*)ws + p.desc_off, s);
+    if (rc) return rc;
+    return enqueue_launches(c, p, ws, s, plain);
+}
+
+int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* stream, bool plain) {
+    if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
+    int rc = validate_frames(frames, n_frames);
+    if (rc) return rc;
+    if (n_frames == 0) return ok();
+    Plan p;
+    make_plan(c, frames, n_frames, plain, p);
+    if (!c->ws || c->ws_bytes < p.total)
+        return fail(POLAR_E_NOMEM, "workspace of %zu bytes < %zu required", c->ws_bytes, p.total);
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(POLAR_E_DEVICE, "cannot select device %d", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (c->graph && !plain) return run_graph(c, p, c->ws, s);
+    return run_plan(c, p, c->ws, c->ws_bytes, s, c->stager, plain);
+}
+
+}  // namespace polar_host
 
 extern "C" int polar_ctx_create(polar_ctx** out, int device, void* workspace, size_t ws_bytes) {
     if (!out) return fail(POLAR_E_INVAL, "out is NULL");
@@ -342,11 +459,6 @@ extern "C" int polar_ctx_create(polar_ctx** out, int device, void* workspace, si
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;
-    e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        delete c;
-        return hip_fail(e, "hipEventCreate");
-    }
     c->ws = workspace;
     c->ws_bytes = workspace ? ws_bytes : 0;
     *out = c;
@@ -357,11 +469,14 @@ extern "C" int polar_ctx_destroy(polar_ctx* c) {
     if (!c) return ok();
     {
         DeviceGuard g(c->device);
-        if (c->staged) {
-            (void)hipEventSynchronize(c->staged);
-            (void)hipEventDestroy(c->staged);
+        c->stager.release();
+        if (!c->graphs.empty()) (void)hipDeviceSynchronize();
+        for (auto& kv : c->graphs) {
+            (void)hipGraphExecDestroy(kv.second.exec);
+            (void)hipHostFree(kv.second.pinned);
         }
-        if (c->staging) (void)hipHostFree(c->staging);
+        c->graphs.clear();
+        if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     }
     delete c;
     return ok();
@@ -400,6 +515,10 @@ extern "C" int polar_ctx_set_option(polar_ctx* c, int option, int64_t value) {
             if (value & 7) return fail(POLAR_E_INVAL, "timing buffer must be 8-byte aligned");
             c->prof = reinterpret_cast<unsigned long long*>((uintptr_t)value);
             return ok();
+        case POLAR_OPT_GRAPH:
+            if (value != 0 && value != 1) return fail(POLAR_E_INVAL, "graph must be 0 or 1");
+            c->graph = (int)value;
+            return ok();
         default:
             return fail(POLAR_E_INVAL, "unknown option %d", option);
     }
@@ -409,10 +528,11 @@ extern "C" int polar_ctx_get_option(polar_ctx* c, int option, int64_t* value) {
     if (!c || !value) return fail(POLAR_E_INVAL, "NULL argument");
     switch (option) {
         case POLAR_OPT_PRUNE: *value = c->prune; return ok();
-        case POLAR_OPT_CUTOVER: *value = eff_cutover(c); return ok();
-        case POLAR_OPT_WG_WAVES: *value = eff_waves(c); return ok();
-        case POLAR_OPT_MAX_SLOTS: *value = eff_max_slots(c); return ok();
+        case POLAR_OPT_CUTOVER: *value = c->cutover; return ok();
+        case POLAR_OPT_WG_WAVES: *value = c->waves; return ok();
+        case POLAR_OPT_MAX_SLOTS: *value = c->max_slots; return ok();
         case POLAR_OPT_TIMING: *value = (int64_t)(uintptr_t)c->prof; return ok();
+        case POLAR_OPT_GRAPH: *value = c->graph; return ok();
         default: return fail(POLAR_E_INVAL, "unknown option %d", option);
     }
 }

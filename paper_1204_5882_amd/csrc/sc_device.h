@@ -38,6 +38,20 @@ struct DecodeLaunch {
 
 extern "C" {
 hipError_t polar_dev_launch_decode(const DecodeLaunch* a);
+// decoder variants (one translation unit each)
+hipError_t polar_dec_c12_ms(const DecodeLaunch* a);
+hipError_t polar_dec_c12_ms_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c12_ms_prune_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_bp(const DecodeLaunch* a);
+hipError_t polar_dec_c12_bp_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_bp_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c12_bp_prune_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c11_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c11_bp_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c10_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c10_bp_prune(const DecodeLaunch* a);
+
 int polar_dev_cutover_supported(int c);
 int polar_dev_waves_supported(int w);
 int64_t polar_dev_slot_bytes(int log2n, int cutover);

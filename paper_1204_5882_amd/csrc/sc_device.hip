@@ -1,994 +1,9 @@
-// Device code of libpolar: polar encoding and successive-cancellation (SC)
-// decoding for gfx950 (CDNA4, wave64).
-//
-// SC decoding (Section 4 of the paper; Arikan's construction cited in
-// Section 3) visits the binary tree of a length-N code depth first.  A node
-// of size M with input LLRs alpha computes
-//     alpha_L[j] = f(alpha[j], alpha[j + M/2])                 (left child)
-//     alpha_R[j] = alpha[j + M/2] + (1 - 2 beta_L[j]) alpha[j]  (right child)
-//     beta       = [beta_L ^ beta_R, beta_R]                    (partial sums)
-// and a leaf decides u = frozen value, or [alpha < 0] for an information bit.
-// Section 4 notes that SC is inherently sequential, so only parallelism
-// across frames and across the elements of one node is available.  This file
-// maps the tree onto the GPU as follows:
-//
-//   * one workgroup decodes one frame at a time, taking frames from a device
-//     queue (persistent launch);
-//   * nodes larger than 2^C (C <= 12) are processed by wide, coalesced sweeps
-//     of the whole workgroup over HBM-resident LLR levels;
-//   * every 2^C-leaf subtree is decoded by a single wavefront entirely in
-//     registers: lane l holds elements k*64 + l, so for node sizes >= 128 the
-//     pair (j, j + M/2) sits in one lane and f/g need no data movement;
-//   * each 64-leaf block is decoded with one element per lane: the half
-//     shift of a node of size M is a DPP row shift (M <= 16) or a gfx950
-//     permlane16/32 swap (M = 32, 64), decisions come from a ballot, and the
-//     partial sums live in one 64-bit scalar word;
-//   * exact pruning: a node whose leaves are all frozen (rate 0) takes
-//     beta = v G_M without any LLR work; a node without frozen leaves
-//     (rate 1) takes beta from the sign / zero state of its LLRs by the
-//     three-state rule, which equals SC even when LLRs are exactly zero.
-//
-// Arithmetic follows the FP32 definitions exactly (no FMA contraction is
-// possible in min-sum: f is a min and a sign, g one addition), so the
-// min-sum decoder is bit-exact against any correct FP32 implementation.
-
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include "sc_device.h"
+// Device code of libpolar outside the decoder variants: the polar encoder,
+// the cross-lane self-test and the dispatch to the decoder variants (each
+// compiled in its own translation unit, see sc_kernels.h).
+#include "sc_kernels.h"
 
 namespace polar_dev {
-
-// ---------------------------------------------------------------------------
-// Cross-lane moves inside a wavefront.
-//   lane_down<H>(x): lane l receives x from lane l + H
-//   lane_up<H>(x):   lane l receives x from lane l - H
-// Only lanes whose partner lies in the same aligned group of 2H lanes are
-// meaningful; callers never read the others.  They must be called with the
-// whole wavefront active (never inside a lane-divergent branch), since an
-// inactive partner lane supplies no data.
-// ---------------------------------------------------------------------------
-template <int H>
-__device__ __forceinline__ uint32_t lane_down(uint32_t x) {
-    if constexpr (H <= 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x100 + H, 0xf, 0xf, false);
-    } else if constexpr (H == 16) {
-        auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-        return r[1];
-    } else {
-        static_assert(H == 32, "lane distance");
-        auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-        return r[1];
-    }
-}
-
-template <int H>
-__device__ __forceinline__ uint32_t lane_up(uint32_t x) {
-    if constexpr (H <= 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x110 + H, 0xf, 0xf, false);
-    } else if constexpr (H == 16) {
-        auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-        return r[0];
-    } else {
-        static_assert(H == 32, "lane distance");
-        auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-        return r[0];
-    }
-}
-
-template <int H>
-__device__ __forceinline__ float lane_downf(float x) {
-    return __uint_as_float(lane_down<H>(__float_as_uint(x)));
-}
-template <int H>
-__device__ __forceinline__ float lane_upf(float x) {
-    return __uint_as_float(lane_up<H>(__float_as_uint(x)));
-}
-template <int H>
-__device__ __forceinline__ uint64_t lane_down64(uint64_t x) {
-    return (uint64_t)lane_down<H>((uint32_t)x) | ((uint64_t)lane_down<H>((uint32_t)(x >> 32)) << 32);
-}
-template <int H>
-__device__ __forceinline__ uint64_t lane_up64(uint64_t x) {
-    return (uint64_t)lane_up<H>((uint32_t)x) | ((uint64_t)lane_up<H>((uint32_t)(x >> 32)) << 32);
-}
-
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-
-__device__ __forceinline__ uint32_t readlane(uint32_t x, int l) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
-}
-__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
-    return (uint64_t)readlane((uint32_t)x, l) | ((uint64_t)readlane((uint32_t)(x >> 32), l) << 32);
-}
-
-// Bits with (bit index & h) == 0, i.e. the lower half of every 2h block.
-__host__ __device__ constexpr uint64_t low_mask64(int h) {
-    return h == 1    ? 0x5555555555555555ull
-           : h == 2  ? 0x3333333333333333ull
-           : h == 4  ? 0x0F0F0F0F0F0F0F0Full
-           : h == 8  ? 0x00FF00FF00FF00FFull
-           : h == 16 ? 0x0000FFFF0000FFFFull
-                     : 0x00000000FFFFFFFFull;
-}
-
-__host__ __device__ constexpr uint64_t ones64(int m) { return m >= 64 ? ~0ull : ((1ull << m) - 1ull); }
-
-// x = u G_m on a word whose bit i is u_i, for a block of m <= 64 bits
-// starting at bit 0: stage h applies x[j] ^= x[j + h] to the lower half of
-// every 2h block.
-__device__ __forceinline__ uint64_t word_transform(uint64_t x, int m) {
-#pragma unroll
-    for (int h = 1; h < 64; h <<= 1)
-        if (h < m) x ^= (x >> h) & low_mask64(h);
-    return x;
-}
-
-// Polar transform across the 64 lanes of a wavefront, applied independently
-// to every bit position of a per-lane word: element index = lane.
-__device__ __forceinline__ uint64_t lane_transform(uint64_t w) {
-    const int l = lane_id();
-    uint64_t p;
-    p = lane_down64<1>(w);  if (!(l & 1))  w ^= p;
-    p = lane_down64<2>(w);  if (!(l & 2))  w ^= p;
-    p = lane_down64<4>(w);  if (!(l & 4))  w ^= p;
-    p = lane_down64<8>(w);  if (!(l & 8))  w ^= p;
-    p = lane_down64<16>(w); if (!(l & 16)) w ^= p;
-    p = lane_down64<32>(w); if (!(l & 32)) w ^= p;
-    return w;
-}
-
-// 64 x 64 bit-matrix transpose: on entry lane r holds row r (bit c = M[r][c]);
-// on exit lane c holds column c (bit r = M[r][c]).  Cross-lane reads only see
-// active lanes, so both partners are fetched with the whole wave active and
-// the result is selected afterwards.
-template <int S>
-__device__ __forceinline__ uint64_t transpose_stage(uint64_t w) {
-    const uint64_t m = low_mask64(S);
-    const uint64_t pu = lane_up64<S>(w);
-    const uint64_t pd = lane_down64<S>(w);
-    const uint64_t from_lo = (w & ~m) | ((pu >> S) & m);  // lanes with bit S set
-    const uint64_t from_hi = (w & m) | ((pd << S) & ~m);  // lanes with bit S clear
-    return (lane_id() & S) ? from_lo : from_hi;
-}
-__device__ __forceinline__ uint64_t transpose64(uint64_t w) {
-    w = transpose_stage<32>(w);
-    w = transpose_stage<16>(w);
-    w = transpose_stage<8>(w);
-    w = transpose_stage<4>(w);
-    w = transpose_stage<2>(w);
-    w = transpose_stage<1>(w);
-    return w;
-}
-
-// ---------------------------------------------------------------------------
-// LLR updates.
-// ---------------------------------------------------------------------------
-// Min-sum check update: sign(a) sign(b) min(|a|, |b|), signs from the IEEE
-// sign bits.
-__device__ __forceinline__ float f_minsum(float a, float b) {
-    float m = fminf(fabsf(a), fabsf(b));
-    uint32_t s = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
-    return __uint_as_float(__float_as_uint(m) | s);
-}
-
-// Exact check update 2 atanh(tanh(a/2) tanh(b/2)) (the phi = log tanh(x/2)
-// form of Section 4) in FP32, on magnitudes A = |a|, B = |b|, m = min(A, B):
-//   m <= 1:  r = log1p(2t / (1 - t)),  t = tanh(A/2) tanh(B/2) <= tanh(1/2)^2,
-//            tanh(x/2) = expm1(x) / (expm1(x) + 2);
-//   m >  1:  r = m + log1p(e^-(A+B)) - log1p(e^-|A-B|)   (r >= 1 - ln 2).
-// Each form is accurate where it is selected.  Everything is straight-line
-// code on the hardware exp2 / log2 (no library calls): both forms are
-// evaluated and one is selected, so the wavefront never diverges here (the
-// decoder's ballots and lane shifts need a fully active wavefront).
-__device__ __forceinline__ float hw_exp(float x) {   // e^x
-    return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
-}
-__device__ __forceinline__ float hw_log(float x) {   // ln x
-    return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
-}
-// expm1(x) for x >= 0: Taylor series to x^9/9! below 1/2 (truncation error
-// < 3e-9 relative), e^x - 1 above (no cancellation there).
-__device__ __forceinline__ float expm1_pos(float x) {
-    float p = 1.0f / 362880.0f;
-    p = fmaf(p, x, 1.0f / 40320.0f);
-    p = fmaf(p, x, 1.0f / 5040.0f);
-    p = fmaf(p, x, 1.0f / 720.0f);
-    p = fmaf(p, x, 1.0f / 120.0f);
-    p = fmaf(p, x, 1.0f / 24.0f);
-    p = fmaf(p, x, 1.0f / 6.0f);
-    p = fmaf(p, x, 0.5f);
-    p = fmaf(p, x, 1.0f);
-    const float small = p * x;
-    const float large = hw_exp(x) - 1.0f;
-    return x < 0.5f ? small : large;
-}
-// log1p(z) for z >= 0 (Goldberg: ln(u) z / (u - 1) with u = 1 + z).
-__device__ __forceinline__ float log1p_pos(float z) {
-    const float u = 1.0f + z;
-    const float d = u - 1.0f;
-    const float r = hw_log(u) * (z / d);
-    return d == 0.0f ? z : r;
-}
-__device__ __forceinline__ float f_boxplus(float a, float b) {
-    const float A = fabsf(a), B = fabsf(b);
-    const float m = fminf(A, B);
-    // tanh form (argument clamped: tanh(x/2) is 1 in FP32 beyond x = 40)
-    const float ea = expm1_pos(fminf(A, 40.0f));
-    const float eb = expm1_pos(fminf(B, 40.0f));
-    const float t = (ea / (ea + 2.0f)) * (eb / (eb + 2.0f));
-    const float r_small = log1p_pos(2.0f * t / (1.0f - t));
-    // log form
-    const float r_large = m + log1p_pos(hw_exp(-(A + B))) - log1p_pos(hw_exp(-fabsf(A - B)));
-    const float r = (m <= 1.0f) ? r_small : r_large;
-    const uint32_t s = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
-    return __uint_as_float(__float_as_uint(r) | s);
-}
-
-template <int FK>
-__device__ __forceinline__ float fupd(float a, float b) {
-    if constexpr (FK == 0) return f_minsum(a, b);
-    else return f_boxplus(a, b);
-}
-
-// g = b + (1 - 2u) a with the sign of a flipped by sgn (0 or 0x80000000).
-__device__ __forceinline__ float gupd(float a, float b, uint32_t sgn) {
-    return b + __uint_as_float(__float_as_uint(a) ^ sgn);
-}
-
-// Rate-1 nodes (no frozen leaf).  In a rate-1 node SC's partial sums equal
-// the hard decisions of the node's LLRs whenever no LLR anywhere inside the
-// node is zero: f keeps the sign product, and g = b + (1 - 2u) a then adds
-// two terms of the sign of b.  (With exact zeros the hard decision is not SC:
-// alpha = (0, -1) gives x-hat = (1, 1).)
-//   min-sum: an LLR inside the node is zero only if the node has an input
-//            that is zero, so "no input LLR is zero" suffices (floor 0);
-//   box-plus: f can also underflow to zero.  For |a|, |b| >= 1 the log form
-//            gives |f| >= min(|a|,|b|) - ln 2, and |g| >= min(|a|,|b|) in a
-//            rate-1 node, so inputs above 1 + L ln 2 keep every LLR of a
-//            node of size 2^L at or above 1.
-// Below the floor the decoder descends into the node like any other, which
-// is SC by construction; its children are checked again.
-template <int FK>
-__host__ __device__ constexpr float rate1_floor(int L) {
-    return FK == 0 ? 0.0f : 1.0f + 0.69314718f * (float)L + 0.01f;
-}
-
-// |x| <= floor, evaluated on the magnitude bits (non-negative floats order
-// like their bit patterns), as one integer compare against a literal.
-template <int FK, int L>
-__device__ __forceinline__ bool below_rate1_floor(float x) {
-    constexpr uint32_t fb = __builtin_bit_cast(uint32_t, rate1_floor<FK>(L));
-    return (__float_as_uint(x) & 0x7fffffffu) <= fb;
-}
-
-__device__ __forceinline__ bool lane_bit(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
-
-// ---------------------------------------------------------------------------
-// 64-leaf block decoder.  The node of size M at lane offset O holds its LLRs
-// in lanes [O, O + M) of a single VGPR.  Partial sums are kept per lane as a
-// sign word (0 or 0x80000000), so f, g and the combine are pure vector code:
-//   f:       a_L = f(a, down_H(a))
-//   g:       a_R = a + up_H(a ^ beta)      (beta of the left child flips a_lo)
-//   combine: beta[j] ^= beta[j + H] for j in [O, O + H)
-// The node type (rate 0, rate 1, repetition, mixed) is a function of the
-// block's frozen mask alone, so it is decided on the scalar unit without
-// waiting for vector results; only the rate-1 floor test and the repetition
-// decision read a ballot.
-// ---------------------------------------------------------------------------
-constexpr uint32_t SIGN = 0x80000000u;
-
-template <int M>
-constexpr int ilog2() { return M <= 1 ? 0 : 1 + ilog2<M / 2>(); }
-
-struct Blk {
-    uint64_t F;       // frozen mask of the block (bit i = leaf i), wave-uniform
-    uint64_t V;       // frozen values of the block (zero outside F), wave-uniform
-    uint64_t TA[7];   // node types per level L (size 2^L), bit O for the node at
-    uint64_t TB[7];   // offset O: type = TA + 2 TB (0 mixed, 1 rate 0,
-                      // 2 rate 1, 3 repetition)
-    uint32_t fv;      // lane i: SIGN if leaf i is frozen with value 1
-    uint32_t w[7];    // lane i: SIGN if bit i of the frozen values re-encoded
-                      // inside every aligned 2^t-block (w[0] = fv)
-    uint32_t beta;    // lane i: partial sum of element i, as a sign word
-    float leaf;       // lane i: decision LLR of leaf i
-    bool has_leaf;    // lane i: leaf i was reached (not inside a pruned node)
-};
-
-__device__ __forceinline__ uint32_t sel_lanes(uint64_t lanes, uint32_t x, uint32_t y) {
-    return lane_bit(lanes) ? x : y;
-}
-
-// Repetition node: every leaf frozen except the last.  SC never needs the
-// f values here (the frozen decisions do not read LLRs): the last leaf's LLR
-// is the chain of g updates down the right spine, each left sibling of size h
-// being a rate-0 node whose partial sums are w[log h] on its lanes.  The node's
-// partial sums are the frozen values re-encoded (w[log M]), all flipped when
-// the last bit is 1 (row M-1 of G_M is all ones).
-template <int H, int M>
-__device__ __forceinline__ float rep_chain(float x, const Blk& B) {
-    if constexpr (H == 0) {
-        return x;
-    } else {
-        const float y = x + __uint_as_float(lane_up<H>(__float_as_uint(x) ^ B.w[ilog2<H>()]));
-        return rep_chain<H / 2, M>(y, B);
-    }
-}
-
-template <int M, bool DUMP>
-__device__ __forceinline__ void rep_node(float a, int O, Blk& B) {
-    const float last = rep_chain<M / 2, M>(a, B);
-    const int il = O + M - 1;
-    if (DUMP && lane_id() == il) {
-        B.leaf = last;
-        B.has_leaf = true;
-    }
-    const bool u = (ballot(last < 0.0f) >> il) & 1ull;
-    B.beta = sel_lanes(ones64(M) << O, B.w[ilog2<M>()] ^ (u ? SIGN : 0u), B.beta);
-}
-
-// ---------------------------------------------------------------------------
-// Small nodes with a known frozen pattern.  Moving a 1 of a channel index to
-// a less significant place, or dropping it, never lowers the Bhattacharyya
-// parameter, so in a code built from those parameters the frozen pattern of
-// every aligned node is closed under that order: an 8-leaf node has one of
-// only ten patterns.  Such a node is decoded by straight-line code generated
-// for its pattern at compile time (no per-node type tests, no loop); any
-// other pattern takes the generic path below.  The partial sums of these
-// nodes are carried as node-local bit words (bit j = element O + j).
-// ---------------------------------------------------------------------------
-#ifndef POLAR_SPEC_M
-#define POLAR_SPEC_M 16
-#endif
-constexpr int SPEC_M = POLAR_SPEC_M;
-static_assert(SPEC_M == 8 || SPEC_M == 16, "specialized node size");
-
-template <int M>
-constexpr uint32_t ones32() { return M >= 32 ? ~0u : (1u << M) - 1u; }
-
-// x G_M on node-local bits (G_M = F^{(x)m}, natural order)
-template <int M>
-__device__ __forceinline__ uint32_t enc_bits(uint32_t x) {
-#pragma unroll
-    for (int h = 1; h < M; h *= 2) x ^= (x >> h) & (uint32_t)low_mask64(h);
-    return x;
-}
-
-// Rate-1 node under min-sum: partial sums from the sign (S) and exact-zero
-// (Z) words of its LLRs by the three-state recursion
-//   left:  S_L = S_lo ^ S_hi,  Z_L = Z_lo | Z_hi
-//   right: Z_R = Z_lo & Z_hi,  S_R = Z_hi ? (S_lo ^ beta_L) : S_hi
-//   beta = [beta_L ^ beta_R, beta_R];  no zeros: beta = S
-// (hard decisions alone are not SC once an LLR is exactly zero).
-template <int M>
-__device__ __forceinline__ uint32_t r1_bits(uint32_t S, uint32_t Z) {
-    if constexpr (M == 1) {
-        return S & ~Z & 1u;
-    } else {
-        if (Z == 0) return S;
-        constexpr int H = M / 2;
-        constexpr uint32_t LO = ones32<H>();
-        const uint32_t bl = r1_bits<H>((S ^ (S >> H)) & LO, (Z | (Z >> H)) & LO);
-        const uint32_t zhi = Z >> H, shi = S >> H;
-        const uint32_t zr = Z & zhi & LO;
-        const uint32_t sr = ((zhi & (S ^ bl)) | (~zhi & shi)) & LO;
-        const uint32_t br = r1_bits<H>(sr, zr);
-        return (bl ^ br) | (br << H);
-    }
-}
-
-// Node of size M at lane offset O with frozen pattern P (bit j = leaf j
-// frozen) and frozen values fv (node-local bits); returns its partial sums.
-template <int M, uint32_t P, int FK, bool DUMP>
-__device__ __forceinline__ uint32_t sl_node(float a, int O, uint32_t fv, Blk& B) {
-    constexpr uint32_t ALL = ones32<M>();
-    if constexpr (P == ALL) {
-        return enc_bits<M>(fv);  // rate 0
-    } else if constexpr (M == 1) {
-        if (DUMP && lane_id() == O) {
-            B.leaf = a;
-            B.has_leaf = true;
-        }
-        return (uint32_t)(ballot(a < 0.0f) >> O) & 1u;
-    } else if constexpr (P == 0 && FK == 0) {
-        const uint32_t S = (uint32_t)(ballot(a < 0.0f) >> O) & ALL;
-        const uint32_t Z = (uint32_t)(ballot(a == 0.0f) >> O) & ALL;
-        return r1_bits<M>(S, Z);
-    } else if constexpr (P == (ALL >> 1)) {
-        const float last = rep_chain<M / 2, M>(a, B);  // repetition
-        const int il = O + M - 1;
-        if (DUMP && lane_id() == il) {
-            B.leaf = last;
-            B.has_leaf = true;
-        }
-        const uint32_t u = (uint32_t)(ballot(last < 0.0f) >> il) & 1u;
-        return enc_bits<M>(fv) ^ ((0u - u) & ALL);
-    } else {
-        constexpr int H = M / 2;
-        constexpr uint32_t LO = ones32<H>();
-        const float c = fupd<FK>(a, lane_downf<H>(a));
-        const uint32_t bl = sl_node<H, (P & LO), FK, DUMP>(c, O, fv & LO, B);
-        const uint32_t sg = lane_bit((uint64_t)bl << O) ? SIGN : 0u;
-        const float d = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ sg));
-        const uint32_t br = sl_node<H, (P >> H), FK, DUMP>(d, O + H, fv >> H, B);
-        return (bl ^ br) | (br << H);
-    }
-}
-
-template <int M, int FK, bool PRUNE, bool DUMP>
-__device__ __forceinline__ void blk_generic(float a, int O, Blk& B);
-
-// Size-SPEC_M node: straight-line code for each closed pattern (10 of 8
-// leaves, 27 of 16 leaves).
-template <int FK, bool DUMP>
-__device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
-    constexpr int M = SPEC_M;
-    const uint32_t p = (uint32_t)(B.F >> O) & ones32<M>();
-    const uint32_t fv = (uint32_t)(B.V >> O) & ones32<M>();
-    uint32_t bits;
-    if constexpr (M == 16) {
-        switch (p) {
-            case 0x0: bits = sl_node<M, 0x0, FK, DUMP>(a, O, fv, B); break;
-            case 0x1: bits = sl_node<M, 0x1, FK, DUMP>(a, O, fv, B); break;
-            case 0x3: bits = sl_node<M, 0x3, FK, DUMP>(a, O, fv, B); break;
-            case 0x7: bits = sl_node<M, 0x7, FK, DUMP>(a, O, fv, B); break;
-            case 0xf: bits = sl_node<M, 0xf, FK, DUMP>(a, O, fv, B); break;
-            case 0x17: bits = sl_node<M, 0x17, FK, DUMP>(a, O, fv, B); break;
-            case 0x1f: bits = sl_node<M, 0x1f, FK, DUMP>(a, O, fv, B); break;
-            case 0x3f: bits = sl_node<M, 0x3f, FK, DUMP>(a, O, fv, B); break;
-            case 0x7f: bits = sl_node<M, 0x7f, FK, DUMP>(a, O, fv, B); break;
-            case 0xff: bits = sl_node<M, 0xff, FK, DUMP>(a, O, fv, B); break;
-            case 0x117: bits = sl_node<M, 0x117, FK, DUMP>(a, O, fv, B); break;
-            case 0x11f: bits = sl_node<M, 0x11f, FK, DUMP>(a, O, fv, B); break;
-            case 0x13f: bits = sl_node<M, 0x13f, FK, DUMP>(a, O, fv, B); break;
-            case 0x17f: bits = sl_node<M, 0x17f, FK, DUMP>(a, O, fv, B); break;
-            case 0x1ff: bits = sl_node<M, 0x1ff, FK, DUMP>(a, O, fv, B); break;
-            case 0x33f: bits = sl_node<M, 0x33f, FK, DUMP>(a, O, fv, B); break;
-            case 0x37f: bits = sl_node<M, 0x37f, FK, DUMP>(a, O, fv, B); break;
-            case 0x3ff: bits = sl_node<M, 0x3ff, FK, DUMP>(a, O, fv, B); break;
-            case 0x77f: bits = sl_node<M, 0x77f, FK, DUMP>(a, O, fv, B); break;
-            case 0x7ff: bits = sl_node<M, 0x7ff, FK, DUMP>(a, O, fv, B); break;
-            case 0xfff: bits = sl_node<M, 0xfff, FK, DUMP>(a, O, fv, B); break;
-            case 0x177f: bits = sl_node<M, 0x177f, FK, DUMP>(a, O, fv, B); break;
-            case 0x17ff: bits = sl_node<M, 0x17ff, FK, DUMP>(a, O, fv, B); break;
-            case 0x1fff: bits = sl_node<M, 0x1fff, FK, DUMP>(a, O, fv, B); break;
-            case 0x3fff: bits = sl_node<M, 0x3fff, FK, DUMP>(a, O, fv, B); break;
-            case 0x7fff: bits = sl_node<M, 0x7fff, FK, DUMP>(a, O, fv, B); break;
-            case 0xffff: bits = sl_node<M, 0xffff, FK, DUMP>(a, O, fv, B); break;
-            default:
-                blk_generic<M, FK, true, DUMP>(a, O, B);
-                bits = (uint32_t)(ballot(B.beta != 0u) >> O) & ones32<M>();
-                break;
-        }
-    } else {
-        switch (p) {
-            case 0x0: bits = sl_node<M, 0x0, FK, DUMP>(a, O, fv, B); break;
-            case 0x1: bits = sl_node<M, 0x1, FK, DUMP>(a, O, fv, B); break;
-            case 0x3: bits = sl_node<M, 0x3, FK, DUMP>(a, O, fv, B); break;
-            case 0x7: bits = sl_node<M, 0x7, FK, DUMP>(a, O, fv, B); break;
-            case 0xf: bits = sl_node<M, 0xf, FK, DUMP>(a, O, fv, B); break;
-            case 0x17: bits = sl_node<M, 0x17, FK, DUMP>(a, O, fv, B); break;
-            case 0x1f: bits = sl_node<M, 0x1f, FK, DUMP>(a, O, fv, B); break;
-            case 0x3f: bits = sl_node<M, 0x3f, FK, DUMP>(a, O, fv, B); break;
-            case 0x7f: bits = sl_node<M, 0x7f, FK, DUMP>(a, O, fv, B); break;
-            case 0xff: bits = sl_node<M, 0xff, FK, DUMP>(a, O, fv, B); break;
-            default:
-                blk_generic<M, FK, true, DUMP>(a, O, B);
-                bits = (uint32_t)(ballot(B.beta != 0u) >> O) & ones32<M>();
-                break;
-        }
-    }
-    B.beta = sel_lanes(ones64(M) << O, lane_bit((uint64_t)bits << O) ? SIGN : 0u, B.beta);
-}
-
-// Node of size M at lane offset O (runtime).  Each size has one copy of its
-// code: the two children are visited by a two-pass loop that is kept rolled,
-// so the code grows with log M rather than with the number of nodes.
-//
-// Both ballots of a node are taken unconditionally at its top and only read
-// inside the shortcut branches: with a ballot placed under the rate-1 test
-// (or an early return nested in that test) this toolchain's -O2/-O3 code
-// returned corrupted partial sums after a failed test, exact at -O1.
-template <int M, int FK, bool PRUNE, bool DUMP>
-__device__ __forceinline__ void blk_node(float a, int O, Blk& B) {
-    if constexpr (PRUNE && M == SPEC_M) {
-        blk_spec<FK, DUMP>(a, O, B);
-    } else {
-        blk_generic<M, FK, PRUNE, DUMP>(a, O, B);
-    }
-}
-
-template <int M, int FK, bool PRUNE, bool DUMP>
-__device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
-    if constexpr (M == 1) {
-        if (DUMP && lane_id() == O) {
-            B.leaf = a;
-            B.has_leaf = true;
-        }
-        // frozen: the revealed value; information bit: [alpha < 0].  Lane O
-        // reads its own frozen bit, so the choice is a lane select.
-        const uint32_t d = lane_bit(B.F) ? B.fv : ((a < 0.0f) ? SIGN : 0u);
-        B.beta = sel_lanes(1ull << O, d, B.beta);
-    } else {
-        constexpr int LG = ilog2<M>();
-        int type = 0;
-        uint64_t neg = 0, low = 0;
-        if constexpr (PRUNE) {
-            neg = ballot(a < 0.0f);
-            low = ballot(below_rate1_floor<FK, LG>(a));
-            type = (int)((B.TA[LG] >> O) & 1ull) | ((int)((B.TB[LG] >> O) & 1ull) << 1);
-            // rate-1 node with an LLR at or under the floor (an exact zero
-            // under min-sum): hard decisions need not be SC there, decode it
-            if (type == 2 && (low & (ones64(M) << O)) != 0) type = 0;
-        }
-        if (type == 0) {
-            constexpr int H = M / 2;
-#pragma clang loop unroll(disable)
-            for (int side = 0; side < 2; ++side) {
-                float c;
-                if (side == 0) {
-                    c = fupd<FK>(a, lane_downf<H>(a));  // left child, lanes [O, O + H)
-                } else {
-                    c = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ B.beta));  // right child
-                }
-                blk_node<H, FK, PRUNE, DUMP>(c, O + side * H, B);
-            }
-            B.beta = sel_lanes(ones64(H) << O, B.beta ^ lane_down<H>(B.beta), B.beta);
-        } else if (type == 1) {
-            B.beta = sel_lanes(ones64(M) << O, B.w[LG], B.beta);
-        } else if (type == 3) {
-            rep_node<M, DUMP>(a, O, B);
-        } else {
-            B.beta = sel_lanes(ones64(M) << O, lane_bit(neg) ? SIGN : 0u, B.beta);
-        }
-    }
-}
-
-// Block set-up from its frozen mask F and frozen values V (wave-uniform).
-__device__ __forceinline__ void blk_init(Blk& B, uint64_t F, uint64_t V) {
-    B.F = F;
-    B.V = V & F;
-    uint64_t W = V & F;
-    B.w[0] = lane_bit(W) ? SIGN : 0u;
-    uint64_t r0 = F, r1 = ~F, rp = ~F;  // size 1: rate 0 = frozen, rate 1 = repetition = information
-#pragma unroll
-    for (int t = 1; t < 7; ++t) {
-        const int h = 1 << (t - 1);
-        W ^= (W >> h) & low_mask64(h);
-        B.w[t] = lane_bit(W) ? SIGN : 0u;
-        rp = r0 & (rp >> h);  // left half rate 0, right half repetition
-        r0 = r0 & (r0 >> h);
-        r1 = r1 & (r1 >> h);
-        B.TA[t] = r0 | rp;
-        B.TB[t] = r1 | rp;
-    }
-    B.TA[0] = B.TB[0] = 0;
-    B.fv = B.w[0];
-    B.beta = 0;
-    B.leaf = 0.0f;
-    B.has_leaf = false;
-}
-
-// ---------------------------------------------------------------------------
-// Subtree of 2^C leaves (C <= 12) decoded by one wavefront.  Level L keeps the
-// LLRs of the current node of size 2^L as elements k*64 + lane,
-// k < 2^(L-6): levels above R in LDS (they are used rarely), levels R and
-// below in registers.  Partial sums of the whole subtree sit in one 64-bit
-// word per lane, bit k = element k*64 + lane (the "lane-packed" layout),
-// which is also how they are exchanged with HBM.
-// ---------------------------------------------------------------------------
-template <int C>
-struct SubCfg {
-    static constexpr int R = C < 9 ? C : 9;  // highest register level
-    // LDS offset (floats) of level L > R: level C at 0, then C-1, ...
-    static constexpr int off(int L) { return (1 << (C + 1)) - (1 << (L + 1)); }
-    static constexpr int lds_floats = (1 << (C + 1)) - (1 << (R + 1));
-};
-
-template <int C>
-struct Lv {
-    float* lds;
-    float a9[8];
-    float a8[4];
-    float a7[2];
-    float a6;
-};
-
-template <int L, int C>
-__device__ __forceinline__ float lv_get(Lv<C>& v, int k) {
-    if constexpr (L > SubCfg<C>::R) return v.lds[SubCfg<C>::off(L) + k * 64 + lane_id()];
-    else if constexpr (L == 9) return v.a9[k];
-    else if constexpr (L == 8) return v.a8[k];
-    else if constexpr (L == 7) return v.a7[k];
-    else return v.a6;
-}
-
-template <int L, int C>
-__device__ __forceinline__ void lv_set(Lv<C>& v, int k, float x) {
-    if constexpr (L > SubCfg<C>::R) v.lds[SubCfg<C>::off(L) + k * 64 + lane_id()] = x;
-    else if constexpr (L == 9) v.a9[k] = x;
-    else if constexpr (L == 8) v.a8[k] = x;
-    else if constexpr (L == 7) v.a7[k] = x;
-    else v.a6 = x;
-}
-
-enum { OP_NONE = 0, OP_F = 1, OP_G = 2 };
-
-// Compute the node of size 2^L from its parent (size 2^(L+1)) by f or g.
-// For g the left sibling covers blocks [b - E, b), E = 2^(L-6).
-template <int L, int C, int FK>
-__device__ __forceinline__ void level_step(Lv<C>& v, int op, int b, uint64_t acc) {
-    constexpr int E = 1 << (L - 6);
-    if (op == OP_F) {
-#pragma unroll
-        for (int k = 0; k < E; ++k) lv_set<L, C>(v, k, fupd<FK>(lv_get<L + 1, C>(v, k), lv_get<L + 1, C>(v, k + E)));
-    } else {
-        const uint64_t x = acc >> (b - E);
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const uint32_t sgn = (uint32_t)((x >> k) & 1ull) << 31;
-            lv_set<L, C>(v, k, gupd(lv_get<L + 1, C>(v, k), lv_get<L + 1, C>(v, k + E), sgn));
-        }
-    }
-}
-
-// Rate-1 shortcut at level L >= 7 (see rate1_floor): on success the partial
-// sums are the hard decisions, bit k of the lane word.
-template <int L, int C, int FK>
-__device__ __forceinline__ bool level_rate1(Lv<C>& v, uint64_t& bits) {
-    constexpr int E = 1 << (L - 6);
-    bool z = false;
-    uint64_t s = 0;
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-        const float x = lv_get<L, C>(v, k);
-        z |= below_rate1_floor<FK, L>(x);
-        s |= (uint64_t)(x < 0.0f) << k;
-    }
-    if (ballot(z) != 0) return false;
-    bits = s;
-    return true;
-}
-
-template <int L, int C>
-__device__ __forceinline__ void level_load_global(Lv<C>& v, const float* src) {
-    constexpr int E = 1 << (L - 6);
-#pragma unroll
-    for (int k = 0; k < E; ++k) lv_set<L, C>(v, k, src[k * 64 + lane_id()]);
-}
-
-struct SubIO {
-    const uint32_t* mask;      // frozen mask words of the subtree
-    const uint32_t* vals;      // frozen value words of the subtree
-    uint32_t* uhat;            // u-hat words of the subtree (out)
-    float* leaf;               // leaf LLRs of the subtree (out) or null
-    uint64_t* beta_out;        // lane-packed partial sums (out) or null
-};
-
-// Decode a subtree of 2^lg leaves, 6 <= lg <= C, on one wavefront.  Input
-// LLRs: at lds + SubCfg<C>::off(lg) when lg > R, else at gsrc (global).
-template <int C, int FK, bool PRUNE, bool DUMP>
-__device__ __forceinline__ void subtree_decode(const SubIO io, int lg, float* lds, const float* gsrc) {
-    constexpr int R = SubCfg<C>::R;
-    const int l = lane_id();
-    const int nb = 1 << (lg - 6);  // 64-leaf blocks
-    Lv<C> v;
-    v.lds = lds;
-
-    // Block words: lane l holds block l's mask and values.
-    uint64_t mw = 0, vw = 0;
-    if (l < nb) {
-        mw = (uint64_t)io.mask[2 * l] | ((uint64_t)io.mask[2 * l + 1] << 32);
-        vw = (uint64_t)io.vals[2 * l] | ((uint64_t)io.vals[2 * l + 1] << 32);
-    }
-    const uint64_t A0 = ballot(l < nb && mw == ~0ull);  // all-frozen blocks
-    const uint64_t A1 = ballot(l < nb && mw == 0ull);   // frozen-free blocks
-    uint64_t vT = 0;                                    // lane l, bit k = value of leaf k*64 + l
-    if (PRUNE && A0 != 0) vT = transpose64(vw);
-
-    if (lg <= R) {
-        switch (lg) {
-            case 9: if constexpr (R >= 9) level_load_global<9, C>(v, gsrc); break;
-            case 8: if constexpr (R >= 8) level_load_global<8, C>(v, gsrc); break;
-            case 7: level_load_global<7, C>(v, gsrc); break;
-            default: v.a6 = gsrc[l]; break;
-        }
-    }
-
-    uint64_t acc = 0;
-    int b = 0;
-    int le = lg;
-    int op = OP_NONE;
-    while (true) {
-        int L = le;
-        int lc;
-        while (true) {
-            const int eb = 1 << (L - 6);
-            const uint64_t rng = ones64(eb) << b;
-            if (PRUNE && (A0 & rng) == rng) {
-                // rate 0: beta = v G over the node, lane-packed
-                uint64_t x = (vT >> b) & ones64(eb);
-                x = word_transform(x, eb);
-                x = lane_transform(x);
-                acc |= x << b;
-                lc = L;
-                break;
-            }
-            if (L == 6) {
-                if (op == OP_F) {
-                    v.a6 = fupd<FK>(v.a7[0], v.a7[1]);
-                } else if (op == OP_G) {
-                    const uint32_t sgn = (uint32_t)((acc >> (b - 1)) & 1ull) << 31;
-                    v.a6 = gupd(v.a7[0], v.a7[1], sgn);
-                }
-                Blk B;
-                blk_init(B, readlane64(mw, b), readlane64(vw, b));
-                blk_node<64, FK, PRUNE, DUMP>(v.a6, 0, B);
-                acc |= (uint64_t)(B.beta >> 31) << b;
-                if (DUMP && B.has_leaf) io.leaf[b * 64 + l] = B.leaf;
-                lc = 6;
-                break;
-            }
-            if (op != OP_NONE) {
-                switch (L) {
-                    case 11: if constexpr (C >= 12) level_step<11, C, FK>(v, op, b, acc); break;
-                    case 10: if constexpr (C >= 11) level_step<10, C, FK>(v, op, b, acc); break;
-                    case 9: if constexpr (C >= 10) level_step<9, C, FK>(v, op, b, acc); break;
-                    case 8: if constexpr (C >= 9) level_step<8, C, FK>(v, op, b, acc); break;
-                    case 7: if constexpr (C >= 8) level_step<7, C, FK>(v, op, b, acc); break;
-                }
-            }
-            uint64_t bits = 0;
-            bool ok = false;
-            if (PRUNE && (A1 & rng) == rng) {
-                switch (L) {
-                    case 12: if constexpr (C >= 12) ok = level_rate1<12, C, FK>(v, bits); break;
-                    case 11: if constexpr (C >= 11) ok = level_rate1<11, C, FK>(v, bits); break;
-                    case 10: if constexpr (C >= 10) ok = level_rate1<10, C, FK>(v, bits); break;
-                    case 9: if constexpr (C >= 9) ok = level_rate1<9, C, FK>(v, bits); break;
-                    case 8: if constexpr (C >= 8) ok = level_rate1<8, C, FK>(v, bits); break;
-                    case 7: ok = level_rate1<7, C, FK>(v, bits); break;
-                }
-            }
-            if (ok) {
-                acc |= bits << b;
-                lc = L;
-                break;
-            }
-            --L;
-            op = OP_F;
-        }
-        // The node at level lc covering blocks [b, b + 2^(lc-6)) is complete.
-        // Every ancestor whose right child has just completed combines its
-        // halves; past the last block that is the whole right spine.
-        b += 1 << (lc - 6);
-        const int top = (b >= nb) ? lg : 6 + __builtin_ctz((unsigned)b);
-        for (int lp = lc + 1; lp <= top; ++lp) {
-            const int e = 1 << (lp - 7);  // blocks per child of the level-lp node
-            const int b0 = b - 2 * e;
-            acc ^= (acc >> e) & (ones64(e) << b0);
-        }
-        if (b >= nb) break;
-        le = top;
-        op = OP_G;
-    }
-
-    if (io.beta_out) io.beta_out[l] = acc;
-
-    // u-hat = x-hat G over the subtree: G over k inside the lane word, then
-    // across lanes; transpose so lane k holds leaves [64k, 64k + 64).
-    uint64_t u = word_transform(acc, nb);
-    u = lane_transform(u);
-    u = transpose64(u);
-    if (l < nb) {
-        io.uhat[2 * l] = (uint32_t)u;
-        io.uhat[2 * l + 1] = (uint32_t)(u >> 32);
-    }
-}
-
-// Frames with N < 64: a single block decoder with the node at offset 0.
-template <int FK, bool PRUNE, bool DUMP>
-__device__ __forceinline__ void tiny_decode(const FrameDesc& fd) {
-    const int l = lane_id();
-    const int n = 1 << fd.log2n;
-    float a = l < n ? fd.llr[l] : 0.0f;
-    Blk B;
-    blk_init(B, fd.mask[0] & (uint32_t)ones64(n), fd.vals[0]);
-    switch (fd.log2n) {
-        case 1: blk_node<2, FK, PRUNE, DUMP>(a, 0, B); break;
-        case 2: blk_node<4, FK, PRUNE, DUMP>(a, 0, B); break;
-        case 3: blk_node<8, FK, PRUNE, DUMP>(a, 0, B); break;
-        case 4: blk_node<16, FK, PRUNE, DUMP>(a, 0, B); break;
-        case 5: blk_node<32, FK, PRUNE, DUMP>(a, 0, B); break;
-        default: blk_node<1, FK, PRUNE, DUMP>(a, 0, B); break;
-    }
-    uint64_t u = word_transform(ballot(B.beta != 0u) & ones64(n), n);
-    if (l == 0) fd.uhat[0] = (uint32_t)u;
-    if (DUMP && l < n && B.has_leaf) fd.leaf[l] = B.leaf;
-}
-
-// ---------------------------------------------------------------------------
-// Workgroup-wide sweeps over HBM-resident LLR levels (nodes larger than 2^C).
-// Rows of 64 consecutive elements; lane = element & 63, so the lane-packed
-// partial sums of the left sibling are read with one coalesced word per row.
-// ---------------------------------------------------------------------------
-constexpr int SWEEP_UNROLL = 8;  // rows in flight per wave
-
-template <int FK>
-__device__ __forceinline__ void sweep_f(const float* __restrict__ in, int64_t half, float* __restrict__ out,
-                                        int wave, int nw) {
-    const int l = lane_id();
-    const int64_t rows = half >> 6;
-    int64_t r = wave;
-    for (; r + (SWEEP_UNROLL - 1) * nw < rows; r += SWEEP_UNROLL * nw) {
-        float x[SWEEP_UNROLL], y[SWEEP_UNROLL];
-#pragma unroll
-        for (int i = 0; i < SWEEP_UNROLL; ++i) {
-            const int64_t j = (r + i * nw) * 64 + l;
-            x[i] = in[j];
-            y[i] = in[j + half];
-        }
-#pragma unroll
-        for (int i = 0; i < SWEEP_UNROLL; ++i) out[(r + i * nw) * 64 + l] = fupd<FK>(x[i], y[i]);
-    }
-    for (; r < rows; r += nw) {
-        const int64_t j = r * 64 + l;
-        out[j] = fupd<FK>(in[j], in[j + half]);
-    }
-}
-
-// beta: lane-packed partial sums of the left child (subtrees of 2^C leaves,
-// 64 words each, bit k of word (s, lane) = element s*2^C + k*64 + lane).
-template <int C>
-__device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t half,
-                                        const uint64_t* __restrict__ beta, float* __restrict__ out,
-                                        int wave, int nw) {
-    constexpr int E = 1 << (C - 6);
-    const int l = lane_id();
-    const int64_t rows = half >> 6;
-    int64_t r = wave;
-    for (; r + (SWEEP_UNROLL - 1) * nw < rows; r += SWEEP_UNROLL * nw) {
-        float x[SWEEP_UNROLL], y[SWEEP_UNROLL];
-        uint64_t w[SWEEP_UNROLL];
-#pragma unroll
-        for (int i = 0; i < SWEEP_UNROLL; ++i) {
-            const int64_t rr = r + i * nw;
-            const int64_t j = rr * 64 + l;
-            x[i] = in[j];
-            y[i] = in[j + half];
-            w[i] = beta[(rr >> (C - 6)) * 64 + l];
-        }
-#pragma unroll
-        for (int i = 0; i < SWEEP_UNROLL; ++i) {
-            const int64_t rr = r + i * nw;
-            const uint32_t sgn = (uint32_t)((w[i] >> (rr & (E - 1))) & 1ull) << 31;
-            out[rr * 64 + l] = gupd(x[i], y[i], sgn);
-        }
-    }
-    for (; r < rows; r += nw) {
-        const int64_t j = r * 64 + l;
-        const uint64_t w = beta[(r >> (C - 6)) * 64 + l];
-        const uint32_t sgn = (uint32_t)((w >> (r & (E - 1))) & 1ull) << 31;
-        out[j] = gupd(in[j], in[j + half], sgn);
-    }
-}
-
-// beta[0 .. words) ^= beta[words .. 2 words)
-__device__ __forceinline__ void combine_words(uint64_t* beta, int64_t words, int tid, int nt) {
-    for (int64_t i = tid; i < words; i += nt) beta[i] ^= beta[i + words];
-}
-
-// Byte offsets inside one frame slot of the workspace.
-__host__ __device__ inline int64_t slot_level_offset(int log2n, int d) {
-    // level d (1 <= d) holds N >> d floats; levels are packed from d = 1
-    const int64_t n = (int64_t)1 << log2n;
-    return (n - (n >> (d - 1))) * 4;
-}
-
-// Optional timing: wave 0 accumulates, in s_memrealtime ticks (100 MHz), the
-// time spent in register-resident subtree decoding.
-__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
-
-template <int C, int FK, bool PRUNE, bool DUMP, int W>
-__device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot, float* lds, uint64_t& sub_ticks) {
-    constexpr int R = SubCfg<C>::R;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6;
-    const int n = fd.log2n;
-    if (n < 6) {
-        if (wave == 0) tiny_decode<FK, PRUNE, DUMP>(fd);
-        return;
-    }
-    if (n <= C) {
-        // the whole frame is one subtree
-        if (n > R) {
-            float* dst = lds + SubCfg<C>::off(n);
-            for (int i = tid; i < (1 << n); i += W * 64) dst[i] = fd.llr[i];
-            __syncthreads();
-        }
-        if (wave == 0) {
-            const uint64_t t0 = now_ticks();
-            SubIO io{fd.mask, fd.vals, fd.uhat, fd.leaf, nullptr};
-            subtree_decode<C, FK, PRUNE, DUMP>(io, n, lds, fd.llr);
-            sub_ticks += now_ticks() - t0;
-        }
-        return;
-    }
-    const int D = n - C;
-    const int64_t N = (int64_t)1 << n;
-    uint64_t* beta = reinterpret_cast<uint64_t*>(slot + slot_level_offset(n, D));
-    auto level = [&](int d) -> float* {
-        return d == 0 ? const_cast<float*>(fd.llr) : reinterpret_cast<float*>(slot + slot_level_offset(n, d));
-    };
-    const int64_t nsub = (int64_t)1 << D;
-    for (int64_t s = 0; s < nsub; ++s) {
-        int t;
-        if (s == 0) {
-            t = D;
-        } else {
-            t = __builtin_ctzll((unsigned long long)s);
-            for (int q = 1; q <= t; ++q) {
-                combine_words(beta + (s - (1ll << q)) * 64, (1ll << (q - 1)) * 64, tid, W * 64);
-                __syncthreads();
-            }
-            // g: parent at depth D - t - 1, right child at depth D - t
-            const int dp = D - t - 1;
-            const int64_t half = N >> (dp + 1);
-            float* dst = (t == 0) ? lds : level(D - t);
-            sweep_g<C>(level(dp), half, beta + (s - (1ll << t)) * 64, dst, wave, W);
-            __syncthreads();
-        }
-        // f chain down to the cutover depth (the cutover node goes to LDS)
-        for (int d = D - t + 1; d <= D; ++d) {
-            const int64_t half = N >> d;
-            float* dst = (d == D) ? lds : level(d);
-            sweep_f<FK>(level(d - 1), half, dst, wave, W);
-            __syncthreads();
-        }
-        if (wave == 0) {
-            const uint64_t t0 = now_ticks();
-            const int64_t base = s << C;
-            SubIO io{fd.mask + (base >> 5), fd.vals + (base >> 5), fd.uhat + (base >> 5),
-                     DUMP ? fd.leaf + base : nullptr, beta + s * 64};
-            subtree_decode<C, FK, PRUNE, DUMP>(io, C, lds, nullptr);
-            sub_ticks += now_ticks() - t0;
-        }
-        __syncthreads();
-    }
-}
-
-template <int C, int FK, bool PRUNE, bool DUMP, int W>
-__global__ __launch_bounds__(W * 64) void k_sc_decode(const FrameDesc* __restrict__ descs, int n_frames,
-                                                       unsigned* __restrict__ counter, uint8_t* slots,
-                                                       int64_t slot_bytes, unsigned long long* prof) {
-    __shared__ float lds[SubCfg<C>::lds_floats > (1 << C) ? SubCfg<C>::lds_floats : (1 << C)];
-    __shared__ int s_frame;
-    uint8_t* slot = slots + (int64_t)blockIdx.x * slot_bytes;
-    while (true) {
-        if (threadIdx.x == 0) s_frame = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int f = s_frame;
-        __syncthreads();
-        if (f >= n_frames) break;
-        const FrameDesc fd = descs[f];
-        uint64_t sub_ticks = 0;
-        const uint64_t t0 = prof ? now_ticks() : 0;
-        decode_frame<C, FK, PRUNE, DUMP, W>(fd, slot, lds, sub_ticks);
-        __syncthreads();
-        if (prof && threadIdx.x == 0) {
-            atomicAdd(prof + 0, (unsigned long long)sub_ticks);
-            atomicAdd(prof + 1, (unsigned long long)(now_ticks() - t0));
-            atomicAdd(prof + 2, 1ull);
-        }
-    }
-}
-
-__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
 
 // ---------------------------------------------------------------------------
 // Encoder x = u G_N on packed words.
@@ -1067,47 +82,38 @@ __global__ void k_lane_selftest(uint32_t* out) {
 
 }  // namespace polar_dev
 
-// ---------------------------------------------------------------------------
-// Host-side launchers (called from the C ABI layer).
-// ---------------------------------------------------------------------------
 using namespace polar_dev;
 
-template <int C, int FK, bool PRUNE, bool DUMP, int W>
-static hipError_t launch_decode_t(const DecodeLaunch& a) {
-    hipLaunchKernelGGL((k_fill_u32), dim3(1), dim3(64), 0, a.stream, a.counter, 1, 0u);
-    hipLaunchKernelGGL((k_sc_decode<C, FK, PRUNE, DUMP, W>), dim3(a.grid), dim3(W * 64), 0, a.stream, a.descs,
-                       a.n_frames, a.counter, a.slots, a.slot_bytes, a.prof);
-    return hipGetLastError();
-}
-
-template <int C, int FK, bool PRUNE, bool DUMP>
-static hipError_t launch_w(const DecodeLaunch& a) {
-    switch (a.waves) {
-        case 4: return launch_decode_t<C, FK, PRUNE, DUMP, 4>(a);
-        case 8: return launch_decode_t<C, FK, PRUNE, DUMP, 8>(a);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <int C, int FK>
-static hipError_t launch_pd(const DecodeLaunch& a) {
-    if (a.prune) return a.dump ? launch_w<C, FK, true, true>(a) : launch_w<C, FK, true, false>(a);
-    return a.dump ? launch_w<C, FK, false, true>(a) : launch_w<C, FK, false, false>(a);
-}
-
-template <int C>
-static hipError_t launch_c(const DecodeLaunch& a) {
-    return a.fk == 0 ? launch_pd<C, 0>(a) : launch_pd<C, 1>(a);
-}
-
 extern "C" hipError_t polar_dev_launch_decode(const DecodeLaunch* a) {
+    if (a->waves != 4 && a->waves != 8) return hipErrorInvalidValue;
+    const int v = (a->fk ? 4 : 0) + (a->prune ? 2 : 0) + (a->dump ? 1 : 0);
     switch (a->cutover) {
-        case 12: return launch_c<12>(*a);
-        default: return hipErrorInvalidValue;
+        case 12:
+            switch (v) {
+                case 0: return polar_dec_c12_ms(a);
+                case 1: return polar_dec_c12_ms_dump(a);
+                case 2: return polar_dec_c12_ms_prune(a);
+                case 3: return polar_dec_c12_ms_prune_dump(a);
+                case 4: return polar_dec_c12_bp(a);
+                case 5: return polar_dec_c12_bp_dump(a);
+                case 6: return polar_dec_c12_bp_prune(a);
+                case 7: return polar_dec_c12_bp_prune_dump(a);
+            }
+            break;
+        // smaller register-resident subtrees: production path only
+        case 11:
+            if (v == 2) return polar_dec_c11_ms_prune(a);
+            if (v == 6) return polar_dec_c11_bp_prune(a);
+            break;
+        case 10:
+            if (v == 2) return polar_dec_c10_ms_prune(a);
+            if (v == 6) return polar_dec_c10_bp_prune(a);
+            break;
     }
+    return hipErrorInvalidValue;
 }
 
-extern "C" int polar_dev_cutover_supported(int c) { return c == 12; }
+extern "C" int polar_dev_cutover_supported(int c) { return c >= 10 && c <= 12; }
 extern "C" int polar_dev_waves_supported(int w) { return w == 4 || w == 8; }
 
 extern "C" int64_t polar_dev_slot_bytes(int log2n, int cutover) {

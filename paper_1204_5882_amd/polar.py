@@ -34,13 +34,23 @@ POLAR_OPT_CUTOVER = 2
 POLAR_OPT_WG_WAVES = 3
 POLAR_OPT_MAX_SLOTS = 4
 POLAR_OPT_TIMING = 5
+POLAR_OPT_GRAPH = 6
+
+POLAR_E_INVAL = -1
+POLAR_E_NOMEM = -2
+POLAR_E_DEVICE = -3
+POLAR_E_BUSY = -4
+POLAR_E_CANCELLED = -5
 
 # every symbol declared in include/polar.h
 EXPORTED = [
     "polar_last_error", "polar_version", "polar_build_frozen_set", "polar_encode",
     "polar_ctx_create", "polar_ctx_destroy", "polar_ctx_set_workspace", "polar_ctx_set_option",
     "polar_ctx_get_option", "polar_workspace_bytes", "polar_sc_decode_batch",
-    "polar_sc_decode_plain", "polar_debug_lane_selftest",
+    "polar_sc_decode_plain", "polar_autotune", "polar_query_launch", "polar_tune_clear",
+    "polar_tune_save", "polar_tune_load", "polar_serve_open", "polar_serve_submit", "polar_serve_poll",
+    "polar_serve_pending", "polar_serve_cancel", "polar_serve_close", "polar_serve",
+    "polar_debug_lane_selftest",
 ]
 
 
@@ -61,6 +71,27 @@ class polar_frame(ctypes.Structure):
         ("leaf_llr", ctypes.c_void_p),
     ]
 
+
+class polar_serve_cfg(ctypes.Structure):
+    _fields_ = [
+        ("arena_bytes", ctypes.c_size_t),
+        ("arena", ctypes.c_void_p),
+        ("max_slots", ctypes.c_int),
+        ("poll_us", ctypes.c_int),
+    ]
+
+
+class polar_completion(ctypes.Structure):
+    _fields_ = [
+        ("req_id", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("latency_s", ctypes.c_double),
+    ]
+
+
+NEXT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(polar_frame), ctypes.POINTER(ctypes.c_uint64))
+DONE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_double)
 
 _lib = None
 
@@ -88,6 +119,18 @@ def load():
         "polar_workspace_bytes": ([P, P, I], SZ),
         "polar_sc_decode_batch": ([P, P, I, P], I),
         "polar_sc_decode_plain": ([P, P, I, P], I),
+        "polar_autotune": ([P, P, I, I, P, P, P, P, P], I),
+        "polar_query_launch": ([P, I, I, I, P, P, P], I),
+        "polar_tune_clear": ([P], I),
+        "polar_tune_save": ([P, ctypes.c_char_p], I),
+        "polar_tune_load": ([P, ctypes.c_char_p], I),
+        "polar_serve_open": ([P, P, P], I),
+        "polar_serve_submit": ([P, P, ctypes.c_uint64], I),
+        "polar_serve_poll": ([P, P, I, P], I),
+        "polar_serve_pending": ([P, P, P, P], I),
+        "polar_serve_cancel": ([P, ctypes.c_uint64], I),
+        "polar_serve_close": ([P], I),
+        "polar_serve": ([P, P, NEXT_FN, DONE_FN, P], I),
         "polar_debug_lane_selftest": ([P, P], I),
     }
     for name, (args, res) in sig.items():
@@ -164,18 +207,22 @@ def lane_selftest(stream=None):
     return out
 
 
+def fill_frame(fr: polar_frame, it: dict) -> None:
+    fr.log2n = int(it["log2n"])
+    fr.f_kind = int(it.get("f_kind", POLAR_F_MINSUM))
+    fr.llr = _ptr(it["llr"])
+    fr.frozen_mask = _ptr(it["frozen_mask"])
+    fr.frozen_vals = _ptr(it["frozen_vals"])
+    fr.u_hat = _ptr(it["u_hat"])
+    fr.leaf_llr = _ptr(it.get("leaf_llr"))
+
+
 def make_frames(items: Sequence[dict]) -> ctypes.Array:
     """items: dicts with log2n, f_kind, llr, frozen_mask, frozen_vals, u_hat,
     optional leaf_llr (torch tensors on the device)."""
     arr = (polar_frame * max(1, len(items)))()
     for i, it in enumerate(items):
-        arr[i].log2n = int(it["log2n"])
-        arr[i].f_kind = int(it.get("f_kind", POLAR_F_MINSUM))
-        arr[i].llr = _ptr(it["llr"])
-        arr[i].frozen_mask = _ptr(it["frozen_mask"])
-        arr[i].frozen_vals = _ptr(it["frozen_vals"])
-        arr[i].u_hat = _ptr(it["u_hat"])
-        arr[i].leaf_llr = _ptr(it.get("leaf_llr"))
+        fill_frame(arr[i], it)
     return arr
 
 
@@ -236,3 +283,127 @@ class Ctx:
         frames = make_frames(items)
         self.ensure_workspace(frames, len(items))
         (self.decode_plain if plain else self.decode_batch)(frames, len(items), stream)
+
+    # autotuner -----------------------------------------------------------
+    def autotune(self, items: Sequence[dict], reps: int = 3, stream=None) -> dict:
+        """Time the built launch configurations on these frames, keep the best
+        for their (f_kind, largest log2n); returns it."""
+        import torch
+
+        items = list(items)
+        frames = make_frames(items)
+        # room for the largest candidate (3 frames in flight per compute unit)
+        need = 0
+        for cut in (10, 11, 12):
+            self.set_option(POLAR_OPT_CUTOVER, cut)
+            self.set_option(POLAR_OPT_MAX_SLOTS, 3 * torch.cuda.get_device_properties(self.device).multi_processor_count)
+            need = max(need, self.workspace_bytes(frames, len(items)))
+        self.set_option(POLAR_OPT_CUTOVER, 0)
+        self.set_option(POLAR_OPT_MAX_SLOTS, 0)
+        if self.workspace is None or self.workspace.numel() < need:
+            self.set_workspace(torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}"))
+        c, w, sl, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(self._lib.polar_autotune(self._h, frames, len(items), int(reps), _stream_handle(stream),
+                                        ctypes.addressof(c), ctypes.addressof(w), ctypes.addressof(sl),
+                                        ctypes.addressof(ms)))
+        return {"cutover": c.value, "waves": w.value, "slots": sl.value, "median_ms": ms.value}
+
+    def query_launch(self, f_kind: int, log2n: int, n_frames: int) -> dict:
+        c, w, sl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.polar_query_launch(self._h, int(f_kind), int(log2n), int(n_frames), ctypes.addressof(c),
+                                            ctypes.addressof(w), ctypes.addressof(sl)))
+        return {"cutover": c.value, "waves": w.value, "slots": sl.value}
+
+    def tune_clear(self):
+        _check(self._lib.polar_tune_clear(self._h))
+
+    def tune_save(self, path: str):
+        _check(self._lib.polar_tune_save(self._h, path.encode()))
+
+    def tune_load(self, path: str):
+        _check(self._lib.polar_tune_load(self._h, path.encode()))
+
+
+class Server:
+    """Non-blocking serving API over a caller-provided device arena (a torch
+    uint8 tensor).  Frames are dicts as for make_frames; the tensors must stay
+    alive until their request completes (the server keeps a reference)."""
+
+    def __init__(self, ctx: Ctx, arena, max_slots: int = 0, poll_us: int = 50):
+        self._lib = load()
+        self.ctx = ctx
+        self.arena = arena
+        self._h = ctypes.c_void_p()
+        cfg = polar_serve_cfg(arena.numel() * arena.element_size(), _ptr(arena), int(max_slots), int(poll_us))
+        _check(self._lib.polar_serve_open(ctx._h, ctypes.addressof(cfg), ctypes.addressof(self._h)))
+        self._keep = {}
+        self._buf = (polar_completion * 1024)()
+
+    def submit(self, item: dict, req_id: int):
+        fr = polar_frame()
+        fill_frame(fr, item)
+        _check(self._lib.polar_serve_submit(self._h, ctypes.addressof(fr), int(req_id)))
+        self._keep[int(req_id)] = item
+
+    def poll(self) -> list:
+        """[(req_id, status, latency_s)] of requests completed since the last poll."""
+        n = ctypes.c_int(0)
+        rc = self._lib.polar_serve_poll(self._h, self._buf, len(self._buf), ctypes.addressof(n))
+        out = [(int(self._buf[k].req_id), int(self._buf[k].status), float(self._buf[k].latency_s))
+               for k in range(n.value)]
+        for rid, _, _ in out:
+            self._keep.pop(rid, None)
+        _check(rc)
+        return out
+
+    def pending(self) -> tuple:
+        q, r, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.polar_serve_pending(self._h, ctypes.addressof(q), ctypes.addressof(r), ctypes.addressof(c)))
+        return q.value, r.value, c.value
+
+    def cancel(self, req_id: int) -> int:
+        """POLAR_OK, or the error code (POLAR_E_BUSY if running, POLAR_E_INVAL if unknown)."""
+        return int(self._lib.polar_serve_cancel(self._h, int(req_id)))
+
+    def close(self):
+        if self._h:
+            rc = self._lib.polar_serve_close(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+            _check(rc)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve(ctx: Ctx, arena, next_request, on_done, max_slots: int = 0, poll_us: int = 50):
+    """Blocking serving loop.  next_request() -> (item, req_id) | None (none
+    yet) | StopIteration-like sentinel "end"; on_done(req_id, status, latency_s)."""
+    lib = load()
+    keep = {}
+
+    def _next(user, fr_ptr, id_ptr):
+        try:
+            r = next_request()
+        except Exception:  # a failing producer ends the stream
+            return 2
+        if r is None:
+            return 1
+        if r == "end":
+            return 2
+        item, rid = r
+        fill_frame(fr_ptr.contents, item)
+        id_ptr[0] = int(rid)
+        keep[int(rid)] = item
+        return 0
+
+    def _done(user, rid, status, lat):
+        keep.pop(int(rid), None)
+        on_done(int(rid), int(status), float(lat))
+
+    nf, df = NEXT_FN(_next), DONE_FN(_done)
+    cfg = polar_serve_cfg(arena.numel() * arena.element_size(), _ptr(arena), int(max_slots), int(poll_us))
+    _check(lib.polar_serve(ctx._h, ctypes.addressof(cfg), nf, df, None))

@@ -1,0 +1,291 @@
+"""GPU tests of the runtime around the decoder, through the C ABI: launch
+variants (register-resident subtree 2^10 / 2^11 / 2^12, 4 or 8 wavefronts),
+graph replay, the autotuner and its table, and the serving loop (admission
+against an arena, continuous batching, cancellation, refusal of oversize
+requests).  Every path must give the oracle's u-hat, and a frame's result
+must not depend on what it was decoded with."""
+import json
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_helpers import biawgn_frames, bits_host, bsc_frames, decode, frame_items, oracle_many
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_5882_amd import polar as lp
+
+    lp.load()
+
+
+def _mixed_frames(n_frames, lo, hi, seed):
+    """Mixed sizes, BSC and BIAWGN, union-bound rates (one mask per frame)."""
+    g = np.random.default_rng(seed)
+    frames = []
+    for f in range(n_frames):
+        log2n = int(g.integers(lo, hi + 1))
+        if f % 2 == 0:
+            p = float(g.uniform(0.01, 0.05))
+            mask, _, _ = oracle.frozen_set(log2n, synth.bsc_z0(p), -1, 0.1)
+            _, fval, llr = synth.frame(seed * 1000 + f, log2n, "bsc", p, mask, lambda v: oracle.encode(log2n, v))
+        else:
+            s = float(g.uniform(0.8, 1.2))
+            mask, _, _ = oracle.frozen_set(log2n, synth.biawgn_z0(s), -1, 0.1)
+            _, fval, llr = synth.frame(seed * 1000 + f, log2n, "biawgn", s, mask, lambda v: oracle.encode(log2n, v))
+        frames.append((llr, mask, fval))
+    return frames
+
+
+# ------------------------------------------------------------ launch variants
+@pytest.mark.parametrize("cut", [10, 11])
+def test_smaller_cutover_minsum_matches_oracle(cut):
+    from paper_1204_5882_amd import polar as lp
+
+    frames = bsc_frames(16, 0.03, 16384, range(7000, 7006)) + bsc_frames(13, 0.02, 1638, range(7100, 7104))
+    refs = [oracle.sc_decode(*fr)[0] for fr in frames]
+    for waves in (4, 8):
+        _say(f"case: cutover {cut}, waves {waves}, min-sum 2^16 and 2^13")
+        us, _ = decode(frames, opts={lp.POLAR_OPT_CUTOVER: cut, lp.POLAR_OPT_WG_WAVES: waves})
+        for k in range(len(frames)):
+            assert np.array_equal(us[k], refs[k]), (cut, waves, k)
+
+
+@pytest.mark.parametrize("cut", [10, 11])
+def test_smaller_cutover_boxplus_equals_cutover_12(cut):
+    """Box-plus results do not depend on where the HBM levels end."""
+    from paper_1204_5882_amd import polar as lp
+
+    frames = biawgn_frames(15, 0.97, 18000, range(7200, 7204))
+    _say(f"case: box-plus cutover {cut} vs 12")
+    ref, _ = decode(frames, f_kind=1, opts={lp.POLAR_OPT_CUTOVER: 12})
+    got, _ = decode(frames, f_kind=1, opts={lp.POLAR_OPT_CUTOVER: cut, lp.POLAR_OPT_WG_WAVES: 8})
+    for k in range(len(frames)):
+        assert np.array_equal(got[k], ref[k]), k
+
+
+def test_large_frame_on_every_cutover():
+    from paper_1204_5882_amd import polar as lp
+
+    frames = bsc_frames(20, 0.03, 262144, [7300])
+    ref = oracle.sc_decode(*frames[0])[0]
+    for cut in (10, 11, 12):
+        _say(f"case: 2^20 min-sum, cutover {cut}")
+        us, _ = decode(frames, opts={lp.POLAR_OPT_CUTOVER: cut})
+        assert np.array_equal(us[0], ref), cut
+
+
+# ---------------------------------------------------------------- graphs
+def test_graph_replay_equals_eager():
+    """Each replay, with eager decodes and synchronisations in between, gives
+    the eager result; a batch with other buffers builds another graph."""
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    frames = _mixed_frames(24, 10, 16, seed=81)
+    refs = [oracle.sc_decode(*fr)[0] for fr in frames]
+    ctx = lp.Ctx(0)
+    items = frame_items(frames)
+    arr = lp.make_frames(items)
+    ctx.ensure_workspace(arr, len(items))
+    ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
+    other = frame_items(frames[:5])
+    for rep in range(4):
+        _say(f"case: graph replay {rep}")
+        for it in items:
+            it["u_hat"].fill_(-1)
+        ctx.decode_batch(arr, len(items))
+        torch.cuda.synchronize()
+        for k, it in enumerate(items):
+            assert np.array_equal(bits_host(it["u_hat"], it["llr"].numel()), refs[k]), (rep, k)
+        # eager work between replays: a different batch without the graph
+        ctx.set_option(lp.POLAR_OPT_GRAPH, 0)
+        ctx.decode(other)
+        torch.cuda.synchronize()
+        for k, it in enumerate(other):
+            assert np.array_equal(bits_host(it["u_hat"], it["llr"].numel()), refs[k])
+        ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
+    _say("case: graph for other buffers")
+    ctx.decode(other)
+    torch.cuda.synchronize()
+    for k, it in enumerate(other):
+        assert np.array_equal(bits_host(it["u_hat"], it["llr"].numel()), refs[k])
+    ctx.close()
+
+
+# ---------------------------------------------------------------- autotuner
+def test_autotune_picks_a_built_config_and_keeps_results():
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    frames = bsc_frames(16, 0.03, 16384, range(7400, 7408))
+    refs = oracle_many(frames)
+    ctx = lp.Ctx(0)
+    items = frame_items(frames)
+    _say("case: autotune 8 x 2^16")
+    best = ctx.autotune(items, reps=2)
+    assert best["cutover"] in (10, 11, 12) and best["waves"] in (4, 8) and best["slots"] >= 1
+    assert best["median_ms"] > 0
+    q = ctx.query_launch(0, 16, 8)
+    assert (q["cutover"], q["waves"]) == (best["cutover"], best["waves"])
+    # other sizes keep the defaults
+    assert ctx.query_launch(0, 18, 8)["cutover"] == 12
+    for it in items:
+        it["u_hat"].fill_(-1)
+    ctx.decode(items)
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        assert np.array_equal(bits_host(it["u_hat"], 1 << 16), refs[k])
+    # explicit options win over the table
+    ctx.set_option(lp.POLAR_OPT_CUTOVER, 12)
+    assert ctx.query_launch(0, 16, 8)["cutover"] == 12
+    ctx.set_option(lp.POLAR_OPT_CUTOVER, 0)
+    # save / load round trip
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        ctx.tune_save(path)
+        data = json.load(open(path))
+        assert data["libpolar_tune"] == 1 and len(data["entries"]) == 1
+        ctx2 = lp.Ctx(0)
+        ctx2.tune_load(path)
+        assert ctx2.query_launch(0, 16, 8) == ctx.query_launch(0, 16, 8)
+        ctx2.tune_clear()
+        assert ctx2.query_launch(0, 16, 8)["cutover"] == 12
+        bad = os.path.join(d, "bad.json")
+        with open(bad, "w") as f:
+            f.write('{"libpolar_tune": 1, "entries": [{"f_kind": 0, "log2n": 16, "cutover": 9, "waves": 4, "slots": 8}]}')
+        with pytest.raises(lp.PolarError):
+            ctx2.tune_load(bad)
+        ctx2.close()
+    ctx.close()
+
+
+# ---------------------------------------------------------------- serving
+def _drain(srv, done, timeout_s=60.0):
+    """Poll until nothing is queued, running or unreported; fills done."""
+    t0 = time.time()
+    while True:
+        for rid, st, lat in srv.poll():
+            done[rid] = (st, lat)
+        if srv.pending() == (0, 0, 0):
+            return done
+        if time.time() - t0 > timeout_s:
+            raise AssertionError(f"serving stalled: {len(done)} done, pending {srv.pending()}")
+        time.sleep(0.0005)
+
+
+def test_serving_results_equal_solo_decodes():
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    frames = _mixed_frames(40, 10, 18, seed=91)
+    refs = [oracle.sc_decode(*fr)[0] for fr in frames]
+    ctx = lp.Ctx(0)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    srv = lp.Server(ctx, arena, max_slots=16, poll_us=0)
+    items = frame_items(frames)
+    done = {}
+    _say("case: serving 40 mixed requests, staggered")
+    for k, it in enumerate(items):
+        srv.submit(it, 100 + k)
+        if k % 7 == 0:  # start batches while other requests still arrive
+            for rid, st, lat in srv.poll():
+                done[rid] = (st, lat)
+    _drain(srv, done)
+    srv.close()
+    torch.cuda.synchronize()
+    assert sorted(done) == [100 + k for k in range(40)]
+    for k, it in enumerate(items):
+        assert done[100 + k][0] == lp.POLAR_OK
+        u = bits_host(it["u_hat"], it["llr"].numel())
+        assert np.array_equal(u, refs[k]), k
+    ctx.close()
+
+
+def test_serving_admission_small_arena_cancel_and_nomem():
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    frames = bsc_frames(18, 0.03, 65536, range(7500, 7506))
+    refs = oracle_many(frames)
+    ctx = lp.Ctx(0)
+    one = ctx.workspace_bytes(lp.make_frames(frame_items(frames[:1])), 1)
+    # room for one 2^18 request at a time: batches of one, run one after another
+    arena = torch.empty(one + 4096, dtype=torch.uint8, device="cuda")
+    srv = lp.Server(ctx, arena, poll_us=0)
+    items = frame_items(frames)
+    big = frame_items(bsc_frames(20, 0.03, 262144, [7600]))[0]
+    _say("case: serving with a one-request arena")
+    for k, it in enumerate(items):
+        srv.submit(it, k)
+    srv.submit(big, 99)  # cannot fit even an empty arena
+    # nothing has started yet: request 5 is still queued and can be cancelled
+    assert srv.cancel(5) == lp.POLAR_OK
+    assert srv.cancel(12345) == lp.POLAR_E_INVAL
+    done = {}
+    t0 = time.time()
+    seen_running = 0
+    while len(done) < 7:
+        for rid, st, lat in srv.poll():
+            done[rid] = (st, lat)
+        q, r, c = srv.pending()
+        seen_running = max(seen_running, r)
+        assert time.time() - t0 < 60, (done, srv.pending())
+        time.sleep(0.0002)
+    srv.close()
+    assert seen_running <= 1  # the arena admits one request at a time
+    assert done[5][0] == lp.POLAR_E_CANCELLED
+    assert done[99][0] == lp.POLAR_E_NOMEM
+    for k in range(5):
+        assert done[k][0] == lp.POLAR_OK and done[k][1] > 0
+        assert np.array_equal(bits_host(items[k]["u_hat"], 1 << 18), refs[k]), k
+    ctx.close()
+
+
+def test_blocking_serve_with_callbacks():
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    frames = _mixed_frames(16, 10, 16, seed=95)
+    refs = [oracle.sc_decode(*fr)[0] for fr in frames]
+    items = frame_items(frames)
+    ctx = lp.Ctx(0)
+    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    queue = list(enumerate(items))
+    results = {}
+
+    def next_request():
+        if not queue:
+            return "end"
+        k, it = queue.pop(0)
+        return it, 500 + k
+
+    def on_done(rid, status, lat):
+        results[rid] = (status, lat)
+
+    _say("case: blocking serve of 16 requests")
+    lp.serve(ctx, arena, next_request, on_done, max_slots=8, poll_us=20)
+    torch.cuda.synchronize()
+    assert sorted(results) == [500 + k for k in range(16)]
+    for k, it in enumerate(items):
+        assert results[500 + k][0] == lp.POLAR_OK
+        assert np.array_equal(bits_host(it["u_hat"], it["llr"].numel()), refs[k]), k
+    ctx.close()

@@ -179,7 +179,7 @@ import re
 
 import synth
 
-SRC = os.path.join(os.path.dirname(__file__), "..", "paper_1204_5882_amd", "csrc", "sc_device.hip")
+SRC = os.path.join(os.path.dirname(__file__), "..", "paper_1204_5882_amd", "csrc", "sc_kernels.h")
 
 
 def _weaker(j, m):
