@@ -299,6 +299,9 @@ def main(argv=None):
     ap.add_argument("--graph", type=int, default=0, help="replay the batch through a HIP graph")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device-to-device copy of this many MiB (a known-size kernel "
+                         "for scaling the HBM byte counters of a profile) before the benchmark")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -312,6 +315,14 @@ def main(argv=None):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_calibration_bytes_read=nbytes, bytes_written=nbytes)), flush=True)
     cfg = CONFIGS[args.config]
     print(f"[bench] generating {args.config}: {cfg['desc']}", file=sys.stderr, flush=True)
     items, host = make_inputs(args.config, lp, torch, dev)

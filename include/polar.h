@@ -95,11 +95,12 @@ int polar_build_frozen_set(int log2n, double z0, int64_t n_frozen, double fer_bo
  */
 int polar_encode(int log2n, int n_frames, const uint32_t* u, uint32_t* x, void* stream);
 
-/* One frame to decode.  All pointers are device pointers. */
+/* One frame to decode.  All pointers are device pointers; llr is 16-byte
+   aligned, the other buffers 4-byte aligned. */
 typedef struct polar_frame {
     int32_t log2n;                /* 1 .. POLAR_MAX_LOG2N                              */
     int32_t f_kind;               /* POLAR_F_MINSUM or POLAR_F_BOXPLUS                  */
-    const float* llr;             /* N channel LLRs                                      */
+    const float* llr;             /* N channel LLRs, 16-byte aligned                     */
     const uint32_t* frozen_mask;  /* max(1, N/32) words, 1 = frozen; may be shared      */
     const uint32_t* frozen_vals;  /* max(1, N/32) words, revealed values of u_F;
                                      bits outside the mask are ignored                 */

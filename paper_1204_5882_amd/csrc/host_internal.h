@@ -33,7 +33,7 @@ size_t align256(size_t x);
 // Launch parameters of one group of frames.
 struct LaunchCfg {
     int cutover = 12;
-    int waves = 4;
+    int waves = 8;
     int slots = 0;  // workgroups (frames in flight)
 };
 

@@ -218,9 +218,10 @@ int validate_frames(const polar_frame* frames, int n_frames) {
             return fail(POLAR_E_INVAL, "frame %d: unknown f_kind %d", i, f.f_kind);
         if (!f.llr || !f.frozen_mask || !f.frozen_vals || !f.u_hat)
             return fail(POLAR_E_INVAL, "frame %d: NULL buffer", i);
-        if (((uintptr_t)f.llr & 3) || ((uintptr_t)f.frozen_mask & 3) || ((uintptr_t)f.frozen_vals & 3) ||
-            ((uintptr_t)f.u_hat & 3) || ((uintptr_t)f.leaf_llr & 3))
-            return fail(POLAR_E_INVAL, "frame %d: buffers must be 4-byte aligned", i);
+        if ((uintptr_t)f.llr & 15) return fail(POLAR_E_INVAL, "frame %d: llr must be 16-byte aligned", i);
+        if (((uintptr_t)f.frozen_mask & 3) || ((uintptr_t)f.frozen_vals & 3) || ((uintptr_t)f.u_hat & 3) ||
+            ((uintptr_t)f.leaf_llr & 3))
+            return fail(POLAR_E_INVAL, "frame %d: bit vectors and leaf_llr must be 4-byte aligned", i);
     }
     return ok();
 }
@@ -234,6 +235,7 @@ LaunchCfg group_cfg(const polar_ctx* c, int fk, int maxlog, int count, bool dump
         return cfg;
     }
     cfg.slots = 2 * c->n_cu;
+    cfg.waves = 8;  // the level sweeps are bound by the bytes in flight per workgroup
     auto it = c->tuned.find({fk, maxlog});
     if (it != c->tuned.end()) cfg = it->second;
     if (c->cutover) cfg.cutover = c->cutover;

@@ -53,7 +53,9 @@ namespace polar_dev {
 template <int H>
 __device__ __forceinline__ uint32_t lane_down(uint32_t x) {
     if constexpr (H <= 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x100 + H, 0xf, 0xf, false);
+        // lanes without a source read 0 (bound_ctrl); the move can then be
+        // folded into the instruction that consumes it
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x100 + H, 0xf, 0xf, true);
     } else if constexpr (H == 16) {
         auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
         return r[1];
@@ -67,7 +69,7 @@ __device__ __forceinline__ uint32_t lane_down(uint32_t x) {
 template <int H>
 __device__ __forceinline__ uint32_t lane_up(uint32_t x) {
     if constexpr (H <= 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x110 + H, 0xf, 0xf, false);
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x110 + H, 0xf, 0xf, true);
     } else if constexpr (H == 16) {
         auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
         return r[0];
@@ -338,8 +340,7 @@ __device__ __forceinline__ void rep_node(float a, int O, Blk& B) {
 // every aligned node is closed under that order: an 8-leaf node has one of
 // only ten patterns.  Such a node is decoded by straight-line code generated
 // for its pattern at compile time (no per-node type tests, no loop); any
-// other pattern takes the generic path below.  The partial sums of these
-// nodes are carried as node-local bit words (bit j = element O + j).
+// other pattern takes the generic path below.
 // ---------------------------------------------------------------------------
 #ifndef POLAR_SPEC_M
 #define POLAR_SPEC_M 16
@@ -349,14 +350,6 @@ static_assert(SPEC_M == 8 || SPEC_M == 16, "specialized node size");
 
 template <int M>
 constexpr uint32_t ones32() { return M >= 32 ? ~0u : (1u << M) - 1u; }
-
-// x G_M on node-local bits (G_M = F^{(x)m}, natural order)
-template <int M>
-__device__ __forceinline__ uint32_t enc_bits(uint32_t x) {
-#pragma unroll
-    for (int h = 1; h < M; h *= 2) x ^= (x >> h) & (uint32_t)low_mask64(h);
-    return x;
-}
 
 // Rate-1 node under min-sum: partial sums from the sign (S) and exact-zero
 // (Z) words of its LLRs by the three-state recursion
@@ -382,22 +375,29 @@ __device__ __forceinline__ uint32_t r1_bits(uint32_t S, uint32_t Z) {
 }
 
 // Node of size M at lane offset O with frozen pattern P (bit j = leaf j
-// frozen) and frozen values fv (node-local bits); returns its partial sums.
+// frozen).  bn carries partial sums as sign words; on entry the lane of every
+// frozen leaf already holds its frozen value, and the node's partial sums are
+// returned on lanes [O, O + M) (other lanes pass through).  Decisions stay in
+// vector registers, so a leaf costs a compare and two selects with no trip
+// through the scalar unit.
 template <int M, uint32_t P, int FK, bool DUMP>
-__device__ __forceinline__ uint32_t sl_node(float a, int O, uint32_t fv, Blk& B) {
+__device__ __forceinline__ uint32_t sl_node(float a, int O, uint32_t bn, Blk& B) {
     constexpr uint32_t ALL = ones32<M>();
+    constexpr int LG = ilog2<M>();
     if constexpr (P == ALL) {
-        return enc_bits<M>(fv);  // rate 0
+        if constexpr (M == 1) return bn;  // frozen leaf: preset
+        else return sel_lanes(ones64(M) << O, B.w[LG], bn);  // rate 0: v G_M
     } else if constexpr (M == 1) {
         if (DUMP && lane_id() == O) {
             B.leaf = a;
             B.has_leaf = true;
         }
-        return (uint32_t)(ballot(a < 0.0f) >> O) & 1u;
+        return sel_lanes(1ull << O, (a < 0.0f) ? SIGN : 0u, bn);
     } else if constexpr (P == 0 && FK == 0) {
         const uint32_t S = (uint32_t)(ballot(a < 0.0f) >> O) & ALL;
         const uint32_t Z = (uint32_t)(ballot(a == 0.0f) >> O) & ALL;
-        return r1_bits<M>(S, Z);
+        const uint64_t bits = (uint64_t)r1_bits<M>(S, Z) << O;
+        return sel_lanes(ones64(M) << O, lane_bit(bits) ? SIGN : 0u, bn);
     } else if constexpr (P == (ALL >> 1)) {
         const float last = rep_chain<M / 2, M>(a, B);  // repetition
         const int il = O + M - 1;
@@ -406,16 +406,15 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, uint32_t fv, Blk& B)
             B.has_leaf = true;
         }
         const uint32_t u = (uint32_t)(ballot(last < 0.0f) >> il) & 1u;
-        return enc_bits<M>(fv) ^ ((0u - u) & ALL);
+        return sel_lanes(ones64(M) << O, B.w[LG] ^ (u << 31), bn);
     } else {
         constexpr int H = M / 2;
         constexpr uint32_t LO = ones32<H>();
         const float c = fupd<FK>(a, lane_downf<H>(a));
-        const uint32_t bl = sl_node<H, (P & LO), FK, DUMP>(c, O, fv & LO, B);
-        const uint32_t sg = lane_bit((uint64_t)bl << O) ? SIGN : 0u;
-        const float d = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ sg));
-        const uint32_t br = sl_node<H, (P >> H), FK, DUMP>(d, O + H, fv >> H, B);
-        return (bl ^ br) | (br << H);
+        bn = sl_node<H, (P & LO), FK, DUMP>(c, O, bn, B);
+        const float d = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bn));
+        bn = sl_node<H, (P >> H), FK, DUMP>(d, O + H, bn, B);
+        return sel_lanes(ones64(H) << O, bn ^ lane_down<H>(bn), bn);
     }
 }
 
@@ -428,61 +427,60 @@ template <int FK, bool DUMP>
 __device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
     constexpr int M = SPEC_M;
     const uint32_t p = (uint32_t)(B.F >> O) & ones32<M>();
-    const uint32_t fv = (uint32_t)(B.V >> O) & ones32<M>();
-    uint32_t bits;
+    uint32_t bn = B.fv;
     if constexpr (M == 16) {
         switch (p) {
-            case 0x0: bits = sl_node<M, 0x0, FK, DUMP>(a, O, fv, B); break;
-            case 0x1: bits = sl_node<M, 0x1, FK, DUMP>(a, O, fv, B); break;
-            case 0x3: bits = sl_node<M, 0x3, FK, DUMP>(a, O, fv, B); break;
-            case 0x7: bits = sl_node<M, 0x7, FK, DUMP>(a, O, fv, B); break;
-            case 0xf: bits = sl_node<M, 0xf, FK, DUMP>(a, O, fv, B); break;
-            case 0x17: bits = sl_node<M, 0x17, FK, DUMP>(a, O, fv, B); break;
-            case 0x1f: bits = sl_node<M, 0x1f, FK, DUMP>(a, O, fv, B); break;
-            case 0x3f: bits = sl_node<M, 0x3f, FK, DUMP>(a, O, fv, B); break;
-            case 0x7f: bits = sl_node<M, 0x7f, FK, DUMP>(a, O, fv, B); break;
-            case 0xff: bits = sl_node<M, 0xff, FK, DUMP>(a, O, fv, B); break;
-            case 0x117: bits = sl_node<M, 0x117, FK, DUMP>(a, O, fv, B); break;
-            case 0x11f: bits = sl_node<M, 0x11f, FK, DUMP>(a, O, fv, B); break;
-            case 0x13f: bits = sl_node<M, 0x13f, FK, DUMP>(a, O, fv, B); break;
-            case 0x17f: bits = sl_node<M, 0x17f, FK, DUMP>(a, O, fv, B); break;
-            case 0x1ff: bits = sl_node<M, 0x1ff, FK, DUMP>(a, O, fv, B); break;
-            case 0x33f: bits = sl_node<M, 0x33f, FK, DUMP>(a, O, fv, B); break;
-            case 0x37f: bits = sl_node<M, 0x37f, FK, DUMP>(a, O, fv, B); break;
-            case 0x3ff: bits = sl_node<M, 0x3ff, FK, DUMP>(a, O, fv, B); break;
-            case 0x77f: bits = sl_node<M, 0x77f, FK, DUMP>(a, O, fv, B); break;
-            case 0x7ff: bits = sl_node<M, 0x7ff, FK, DUMP>(a, O, fv, B); break;
-            case 0xfff: bits = sl_node<M, 0xfff, FK, DUMP>(a, O, fv, B); break;
-            case 0x177f: bits = sl_node<M, 0x177f, FK, DUMP>(a, O, fv, B); break;
-            case 0x17ff: bits = sl_node<M, 0x17ff, FK, DUMP>(a, O, fv, B); break;
-            case 0x1fff: bits = sl_node<M, 0x1fff, FK, DUMP>(a, O, fv, B); break;
-            case 0x3fff: bits = sl_node<M, 0x3fff, FK, DUMP>(a, O, fv, B); break;
-            case 0x7fff: bits = sl_node<M, 0x7fff, FK, DUMP>(a, O, fv, B); break;
-            case 0xffff: bits = sl_node<M, 0xffff, FK, DUMP>(a, O, fv, B); break;
+            case 0x0: bn = sl_node<M, 0x0, FK, DUMP>(a, O, bn, B); break;
+            case 0x1: bn = sl_node<M, 0x1, FK, DUMP>(a, O, bn, B); break;
+            case 0x3: bn = sl_node<M, 0x3, FK, DUMP>(a, O, bn, B); break;
+            case 0x7: bn = sl_node<M, 0x7, FK, DUMP>(a, O, bn, B); break;
+            case 0xf: bn = sl_node<M, 0xf, FK, DUMP>(a, O, bn, B); break;
+            case 0x17: bn = sl_node<M, 0x17, FK, DUMP>(a, O, bn, B); break;
+            case 0x1f: bn = sl_node<M, 0x1f, FK, DUMP>(a, O, bn, B); break;
+            case 0x3f: bn = sl_node<M, 0x3f, FK, DUMP>(a, O, bn, B); break;
+            case 0x7f: bn = sl_node<M, 0x7f, FK, DUMP>(a, O, bn, B); break;
+            case 0xff: bn = sl_node<M, 0xff, FK, DUMP>(a, O, bn, B); break;
+            case 0x117: bn = sl_node<M, 0x117, FK, DUMP>(a, O, bn, B); break;
+            case 0x11f: bn = sl_node<M, 0x11f, FK, DUMP>(a, O, bn, B); break;
+            case 0x13f: bn = sl_node<M, 0x13f, FK, DUMP>(a, O, bn, B); break;
+            case 0x17f: bn = sl_node<M, 0x17f, FK, DUMP>(a, O, bn, B); break;
+            case 0x1ff: bn = sl_node<M, 0x1ff, FK, DUMP>(a, O, bn, B); break;
+            case 0x33f: bn = sl_node<M, 0x33f, FK, DUMP>(a, O, bn, B); break;
+            case 0x37f: bn = sl_node<M, 0x37f, FK, DUMP>(a, O, bn, B); break;
+            case 0x3ff: bn = sl_node<M, 0x3ff, FK, DUMP>(a, O, bn, B); break;
+            case 0x77f: bn = sl_node<M, 0x77f, FK, DUMP>(a, O, bn, B); break;
+            case 0x7ff: bn = sl_node<M, 0x7ff, FK, DUMP>(a, O, bn, B); break;
+            case 0xfff: bn = sl_node<M, 0xfff, FK, DUMP>(a, O, bn, B); break;
+            case 0x177f: bn = sl_node<M, 0x177f, FK, DUMP>(a, O, bn, B); break;
+            case 0x17ff: bn = sl_node<M, 0x17ff, FK, DUMP>(a, O, bn, B); break;
+            case 0x1fff: bn = sl_node<M, 0x1fff, FK, DUMP>(a, O, bn, B); break;
+            case 0x3fff: bn = sl_node<M, 0x3fff, FK, DUMP>(a, O, bn, B); break;
+            case 0x7fff: bn = sl_node<M, 0x7fff, FK, DUMP>(a, O, bn, B); break;
+            case 0xffff: bn = sl_node<M, 0xffff, FK, DUMP>(a, O, bn, B); break;
             default:
                 blk_generic<M, FK, true, DUMP>(a, O, B);
-                bits = (uint32_t)(ballot(B.beta != 0u) >> O) & ones32<M>();
+                bn = B.beta;
                 break;
         }
     } else {
         switch (p) {
-            case 0x0: bits = sl_node<M, 0x0, FK, DUMP>(a, O, fv, B); break;
-            case 0x1: bits = sl_node<M, 0x1, FK, DUMP>(a, O, fv, B); break;
-            case 0x3: bits = sl_node<M, 0x3, FK, DUMP>(a, O, fv, B); break;
-            case 0x7: bits = sl_node<M, 0x7, FK, DUMP>(a, O, fv, B); break;
-            case 0xf: bits = sl_node<M, 0xf, FK, DUMP>(a, O, fv, B); break;
-            case 0x17: bits = sl_node<M, 0x17, FK, DUMP>(a, O, fv, B); break;
-            case 0x1f: bits = sl_node<M, 0x1f, FK, DUMP>(a, O, fv, B); break;
-            case 0x3f: bits = sl_node<M, 0x3f, FK, DUMP>(a, O, fv, B); break;
-            case 0x7f: bits = sl_node<M, 0x7f, FK, DUMP>(a, O, fv, B); break;
-            case 0xff: bits = sl_node<M, 0xff, FK, DUMP>(a, O, fv, B); break;
+            case 0x0: bn = sl_node<M, 0x0, FK, DUMP>(a, O, bn, B); break;
+            case 0x1: bn = sl_node<M, 0x1, FK, DUMP>(a, O, bn, B); break;
+            case 0x3: bn = sl_node<M, 0x3, FK, DUMP>(a, O, bn, B); break;
+            case 0x7: bn = sl_node<M, 0x7, FK, DUMP>(a, O, bn, B); break;
+            case 0xf: bn = sl_node<M, 0xf, FK, DUMP>(a, O, bn, B); break;
+            case 0x17: bn = sl_node<M, 0x17, FK, DUMP>(a, O, bn, B); break;
+            case 0x1f: bn = sl_node<M, 0x1f, FK, DUMP>(a, O, bn, B); break;
+            case 0x3f: bn = sl_node<M, 0x3f, FK, DUMP>(a, O, bn, B); break;
+            case 0x7f: bn = sl_node<M, 0x7f, FK, DUMP>(a, O, bn, B); break;
+            case 0xff: bn = sl_node<M, 0xff, FK, DUMP>(a, O, bn, B); break;
             default:
                 blk_generic<M, FK, true, DUMP>(a, O, B);
-                bits = (uint32_t)(ballot(B.beta != 0u) >> O) & ones32<M>();
+                bn = B.beta;
                 break;
         }
     }
-    B.beta = sel_lanes(ones64(M) << O, lane_bit((uint64_t)bits << O) ? SIGN : 0u, B.beta);
+    B.beta = sel_lanes(ones64(M) << O, bn, B.beta);
 }
 
 // Node of size M at lane offset O (runtime).  Each size has one copy of its
@@ -812,68 +810,85 @@ __device__ __forceinline__ void tiny_decode(const FrameDesc& fd) {
 }
 
 // ---------------------------------------------------------------------------
-// Workgroup-wide sweeps over HBM-resident LLR levels (nodes larger than 2^C).
-// Rows of 64 consecutive elements; lane = element & 63, so the lane-packed
-// partial sums of the left sibling are read with one coalesced word per row.
+// Workgroup-wide sweeps over the LLR levels of nodes larger than 2^C (in HBM,
+// or in the LDS tier).  Each lane handles 4 consecutive elements with 16-byte
+// accesses, rows of 256 elements per wave instruction, SWEEP_UNROLL rows in
+// flight per wave: these sweeps are bound by the bytes one workgroup keeps in
+// flight, not by instruction count.
 // ---------------------------------------------------------------------------
 constexpr int SWEEP_UNROLL = 8;  // rows in flight per wave
+
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+
+template <int FK>
+__device__ __forceinline__ float4 f4(float4 a, float4 b) {
+    return make_float4(fupd<FK>(a.x, b.x), fupd<FK>(a.y, b.y), fupd<FK>(a.z, b.z), fupd<FK>(a.w, b.w));
+}
 
 template <int FK>
 __device__ __forceinline__ void sweep_f(const float* __restrict__ in, int64_t half, float* __restrict__ out,
                                         int wave, int nw) {
-    const int l = lane_id();
-    const int64_t rows = half >> 6;
+    const int l4 = lane_id() * 4;
+    const int64_t rows = half >> 8;
     int64_t r = wave;
     for (; r + (SWEEP_UNROLL - 1) * nw < rows; r += SWEEP_UNROLL * nw) {
-        float x[SWEEP_UNROLL], y[SWEEP_UNROLL];
+        float4 x[SWEEP_UNROLL], y[SWEEP_UNROLL];
 #pragma unroll
         for (int i = 0; i < SWEEP_UNROLL; ++i) {
-            const int64_t j = (r + i * nw) * 64 + l;
-            x[i] = in[j];
-            y[i] = in[j + half];
+            const int64_t j = (r + i * nw) * 256 + l4;
+            x[i] = ld4(in + j);
+            y[i] = ld4(in + j + half);
         }
 #pragma unroll
-        for (int i = 0; i < SWEEP_UNROLL; ++i) out[(r + i * nw) * 64 + l] = fupd<FK>(x[i], y[i]);
+        for (int i = 0; i < SWEEP_UNROLL; ++i) st4(out + (r + i * nw) * 256 + l4, f4<FK>(x[i], y[i]));
     }
     for (; r < rows; r += nw) {
-        const int64_t j = r * 64 + l;
-        out[j] = fupd<FK>(in[j], in[j + half]);
+        const int64_t j = r * 256 + l4;
+        st4(out + j, f4<FK>(ld4(in + j), ld4(in + j + half)));
     }
 }
 
 // beta: lane-packed partial sums of the left child (subtrees of 2^C leaves,
 // 64 words each, bit k of word (s, lane) = element s*2^C + k*64 + lane).
+// Element j reads bit (j >> 6) mod 2^(C-6) of word (j >> C)*64 + (j & 63);
+// the 4 elements of a lane use 4 consecutive words.
+template <int C>
+__device__ __forceinline__ float4 g4(float4 a, float4 b, const uint64_t* __restrict__ beta, int64_t j) {
+    constexpr int E = 1 << (C - 6);
+    const uint64_t* w = beta + (j >> C) * 64 + (j & 63);
+    const ulonglong2 w01 = *reinterpret_cast<const ulonglong2*>(w);
+    const ulonglong2 w23 = *reinterpret_cast<const ulonglong2*>(w + 2);
+    const int k = (int)((j >> 6) & (E - 1));
+    const auto sg = [k](uint64_t x) { return (uint32_t)((x >> k) & 1ull) << 31; };
+    return make_float4(gupd(a.x, b.x, sg(w01.x)), gupd(a.y, b.y, sg(w01.y)), gupd(a.z, b.z, sg(w23.x)),
+                       gupd(a.w, b.w, sg(w23.y)));
+}
+
 template <int C>
 __device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t half,
                                         const uint64_t* __restrict__ beta, float* __restrict__ out,
                                         int wave, int nw) {
-    constexpr int E = 1 << (C - 6);
-    const int l = lane_id();
-    const int64_t rows = half >> 6;
+    const int l4 = lane_id() * 4;
+    const int64_t rows = half >> 8;
     int64_t r = wave;
     for (; r + (SWEEP_UNROLL - 1) * nw < rows; r += SWEEP_UNROLL * nw) {
-        float x[SWEEP_UNROLL], y[SWEEP_UNROLL];
-        uint64_t w[SWEEP_UNROLL];
+        float4 x[SWEEP_UNROLL], y[SWEEP_UNROLL];
 #pragma unroll
         for (int i = 0; i < SWEEP_UNROLL; ++i) {
-            const int64_t rr = r + i * nw;
-            const int64_t j = rr * 64 + l;
-            x[i] = in[j];
-            y[i] = in[j + half];
-            w[i] = beta[(rr >> (C - 6)) * 64 + l];
+            const int64_t j = (r + i * nw) * 256 + l4;
+            x[i] = ld4(in + j);
+            y[i] = ld4(in + j + half);
         }
 #pragma unroll
         for (int i = 0; i < SWEEP_UNROLL; ++i) {
-            const int64_t rr = r + i * nw;
-            const uint32_t sgn = (uint32_t)((w[i] >> (rr & (E - 1))) & 1ull) << 31;
-            out[rr * 64 + l] = gupd(x[i], y[i], sgn);
+            const int64_t j = (r + i * nw) * 256 + l4;
+            st4(out + j, g4<C>(x[i], y[i], beta, j));
         }
     }
     for (; r < rows; r += nw) {
-        const int64_t j = r * 64 + l;
-        const uint64_t w = beta[(r >> (C - 6)) * 64 + l];
-        const uint32_t sgn = (uint32_t)((w >> (r & (E - 1))) & 1ull) << 31;
-        out[j] = gupd(in[j], in[j + half], sgn);
+        const int64_t j = r * 256 + l4;
+        st4(out + j, g4<C>(ld4(in + j), ld4(in + j + half), beta, j));
     }
 }
 
@@ -894,7 +909,8 @@ __host__ __device__ inline int64_t slot_level_offset(int log2n, int d) {
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
 template <int C, int FK, bool PRUNE, bool DUMP>
-__device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot, float* lds, uint64_t& sub_ticks) {
+__device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot, float* lds, float* tier,
+                                             uint64_t& sub_ticks) {
     const int W = (int)(blockDim.x >> 6);  // wavefronts in the workgroup
     constexpr int R = SubCfg<C>::R;
     const int tid = threadIdx.x;
@@ -922,8 +938,14 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
     const int D = n - C;
     const int64_t N = (int64_t)1 << n;
     uint64_t* beta = reinterpret_cast<uint64_t*>(slot + slot_level_offset(n, D));
+    // Levels of the two depths above the cutover live in LDS (the "tier"),
+    // so that most subtree steps make no HBM round trip; deeper-up levels
+    // are in the frame's slot in HBM.
     auto level = [&](int d) -> float* {
-        return d == 0 ? const_cast<float*>(fd.llr) : reinterpret_cast<float*>(slot + slot_level_offset(n, d));
+        if (d == 0) return const_cast<float*>(fd.llr);
+        if (d == D - 1) return tier;
+        if (d == D - 2) return tier + (2 << C);
+        return reinterpret_cast<float*>(slot + slot_level_offset(n, d));
     };
     const int64_t nsub = (int64_t)1 << D;
     for (int64_t s = 0; s < nsub; ++s) {
@@ -962,6 +984,9 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
     }
 }
 
+template <int C>
+constexpr int TIER_FLOATS = (2 << C) + (4 << C);
+
 // One kernel serves every workgroup size up to MAXW wavefronts (its register
 // budget is the one of MAXW).
 template <int C, int FK, bool PRUNE, bool DUMP, int MAXW>
@@ -969,6 +994,7 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __rest
                                                        unsigned* __restrict__ counter, uint8_t* slots,
                                                        int64_t slot_bytes, unsigned long long* prof) {
     __shared__ float lds[SubCfg<C>::lds_floats > (1 << C) ? SubCfg<C>::lds_floats : (1 << C)];
+    __shared__ float tier[TIER_FLOATS<C>];  // LLR levels of sizes 2^(C+1) and 2^(C+2)
     __shared__ int s_frame;
     uint8_t* slot = slots + (int64_t)blockIdx.x * slot_bytes;
     while (true) {
@@ -980,7 +1006,7 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __rest
         const FrameDesc fd = descs[f];
         uint64_t sub_ticks = 0;
         const uint64_t t0 = prof ? now_ticks() : 0;
-        decode_frame<C, FK, PRUNE, DUMP>(fd, slot, lds, sub_ticks);
+        decode_frame<C, FK, PRUNE, DUMP>(fd, slot, lds, tier, sub_ticks);
         __syncthreads();
         if (prof && threadIdx.x == 0) {
             atomicAdd(prof + 0, (unsigned long long)sub_ticks);
