@@ -374,30 +374,40 @@ __device__ __forceinline__ uint32_t r1_bits(uint32_t S, uint32_t Z) {
     }
 }
 
+// Lanes whose index has bit H clear: the left halves of all aligned nodes of
+// size 2H.
+template <int H>
+constexpr uint64_t left_lanes() {
+    uint64_t m = 0;
+    for (int l = 0; l < 64; ++l)
+        if ((l & H) == 0) m |= 1ull << l;
+    return m;
+}
+
 // Node of size M at lane offset O with frozen pattern P (bit j = leaf j
-// frozen).  bn carries partial sums as sign words; on entry the lane of every
-// frozen leaf already holds its frozen value, and the node's partial sums are
-// returned on lanes [O, O + M) (other lanes pass through).  Decisions stay in
-// vector registers, so a leaf costs a compare and two selects with no trip
-// through the scalar unit.
+// frozen).  Returns the node's partial sums as sign words, meaningful on the
+// node's lanes [O, O + M) only: values on other lanes are left undefined, so
+// leaves and rate-0 / repetition nodes need no lane selects, and a combine
+// picks its halves with a constant lane mask.  Decisions stay in vector
+// registers except where a ballot is inherent (rate-1 zero test, repetition
+// decision).
 template <int M, uint32_t P, int FK, bool DUMP>
-__device__ __forceinline__ uint32_t sl_node(float a, int O, uint32_t bn, Blk& B) {
+__device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
     constexpr uint32_t ALL = ones32<M>();
     constexpr int LG = ilog2<M>();
     if constexpr (P == ALL) {
-        if constexpr (M == 1) return bn;  // frozen leaf: preset
-        else return sel_lanes(ones64(M) << O, B.w[LG], bn);  // rate 0: v G_M
+        return B.w[LG];  // rate 0 (a frozen leaf: its revealed value)
     } else if constexpr (M == 1) {
         if (DUMP && lane_id() == O) {
             B.leaf = a;
             B.has_leaf = true;
         }
-        return sel_lanes(1ull << O, (a < 0.0f) ? SIGN : 0u, bn);
+        return (a < 0.0f) ? SIGN : 0u;
     } else if constexpr (P == 0 && FK == 0) {
         const uint32_t S = (uint32_t)(ballot(a < 0.0f) >> O) & ALL;
         const uint32_t Z = (uint32_t)(ballot(a == 0.0f) >> O) & ALL;
         const uint64_t bits = (uint64_t)r1_bits<M>(S, Z) << O;
-        return sel_lanes(ones64(M) << O, lane_bit(bits) ? SIGN : 0u, bn);
+        return lane_bit(bits) ? SIGN : 0u;
     } else if constexpr (P == (ALL >> 1)) {
         const float last = rep_chain<M / 2, M>(a, B);  // repetition
         const int il = O + M - 1;
@@ -406,15 +416,15 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, uint32_t bn, Blk& B)
             B.has_leaf = true;
         }
         const uint32_t u = (uint32_t)(ballot(last < 0.0f) >> il) & 1u;
-        return sel_lanes(ones64(M) << O, B.w[LG] ^ (u << 31), bn);
+        return B.w[LG] ^ (u << 31);
     } else {
         constexpr int H = M / 2;
         constexpr uint32_t LO = ones32<H>();
         const float c = fupd<FK>(a, lane_downf<H>(a));
-        bn = sl_node<H, (P & LO), FK, DUMP>(c, O, bn, B);
-        const float d = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bn));
-        bn = sl_node<H, (P >> H), FK, DUMP>(d, O + H, bn, B);
-        return sel_lanes(ones64(H) << O, bn ^ lane_down<H>(bn), bn);
+        const uint32_t bl = sl_node<H, (P & LO), FK, DUMP>(c, O, B);
+        const float d = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bl));
+        const uint32_t br = sl_node<H, (P >> H), FK, DUMP>(d, O + H, B);
+        return sel_lanes(left_lanes<H>(), bl ^ lane_down<H>(br), br);
     }
 }
 
@@ -427,36 +437,36 @@ template <int FK, bool DUMP>
 __device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
     constexpr int M = SPEC_M;
     const uint32_t p = (uint32_t)(B.F >> O) & ones32<M>();
-    uint32_t bn = B.fv;
+    uint32_t bn;
     if constexpr (M == 16) {
         switch (p) {
-            case 0x0: bn = sl_node<M, 0x0, FK, DUMP>(a, O, bn, B); break;
-            case 0x1: bn = sl_node<M, 0x1, FK, DUMP>(a, O, bn, B); break;
-            case 0x3: bn = sl_node<M, 0x3, FK, DUMP>(a, O, bn, B); break;
-            case 0x7: bn = sl_node<M, 0x7, FK, DUMP>(a, O, bn, B); break;
-            case 0xf: bn = sl_node<M, 0xf, FK, DUMP>(a, O, bn, B); break;
-            case 0x17: bn = sl_node<M, 0x17, FK, DUMP>(a, O, bn, B); break;
-            case 0x1f: bn = sl_node<M, 0x1f, FK, DUMP>(a, O, bn, B); break;
-            case 0x3f: bn = sl_node<M, 0x3f, FK, DUMP>(a, O, bn, B); break;
-            case 0x7f: bn = sl_node<M, 0x7f, FK, DUMP>(a, O, bn, B); break;
-            case 0xff: bn = sl_node<M, 0xff, FK, DUMP>(a, O, bn, B); break;
-            case 0x117: bn = sl_node<M, 0x117, FK, DUMP>(a, O, bn, B); break;
-            case 0x11f: bn = sl_node<M, 0x11f, FK, DUMP>(a, O, bn, B); break;
-            case 0x13f: bn = sl_node<M, 0x13f, FK, DUMP>(a, O, bn, B); break;
-            case 0x17f: bn = sl_node<M, 0x17f, FK, DUMP>(a, O, bn, B); break;
-            case 0x1ff: bn = sl_node<M, 0x1ff, FK, DUMP>(a, O, bn, B); break;
-            case 0x33f: bn = sl_node<M, 0x33f, FK, DUMP>(a, O, bn, B); break;
-            case 0x37f: bn = sl_node<M, 0x37f, FK, DUMP>(a, O, bn, B); break;
-            case 0x3ff: bn = sl_node<M, 0x3ff, FK, DUMP>(a, O, bn, B); break;
-            case 0x77f: bn = sl_node<M, 0x77f, FK, DUMP>(a, O, bn, B); break;
-            case 0x7ff: bn = sl_node<M, 0x7ff, FK, DUMP>(a, O, bn, B); break;
-            case 0xfff: bn = sl_node<M, 0xfff, FK, DUMP>(a, O, bn, B); break;
-            case 0x177f: bn = sl_node<M, 0x177f, FK, DUMP>(a, O, bn, B); break;
-            case 0x17ff: bn = sl_node<M, 0x17ff, FK, DUMP>(a, O, bn, B); break;
-            case 0x1fff: bn = sl_node<M, 0x1fff, FK, DUMP>(a, O, bn, B); break;
-            case 0x3fff: bn = sl_node<M, 0x3fff, FK, DUMP>(a, O, bn, B); break;
-            case 0x7fff: bn = sl_node<M, 0x7fff, FK, DUMP>(a, O, bn, B); break;
-            case 0xffff: bn = sl_node<M, 0xffff, FK, DUMP>(a, O, bn, B); break;
+            case 0x0: bn = sl_node<M, 0x0, FK, DUMP>(a, O, B); break;
+            case 0x1: bn = sl_node<M, 0x1, FK, DUMP>(a, O, B); break;
+            case 0x3: bn = sl_node<M, 0x3, FK, DUMP>(a, O, B); break;
+            case 0x7: bn = sl_node<M, 0x7, FK, DUMP>(a, O, B); break;
+            case 0xf: bn = sl_node<M, 0xf, FK, DUMP>(a, O, B); break;
+            case 0x17: bn = sl_node<M, 0x17, FK, DUMP>(a, O, B); break;
+            case 0x1f: bn = sl_node<M, 0x1f, FK, DUMP>(a, O, B); break;
+            case 0x3f: bn = sl_node<M, 0x3f, FK, DUMP>(a, O, B); break;
+            case 0x7f: bn = sl_node<M, 0x7f, FK, DUMP>(a, O, B); break;
+            case 0xff: bn = sl_node<M, 0xff, FK, DUMP>(a, O, B); break;
+            case 0x117: bn = sl_node<M, 0x117, FK, DUMP>(a, O, B); break;
+            case 0x11f: bn = sl_node<M, 0x11f, FK, DUMP>(a, O, B); break;
+            case 0x13f: bn = sl_node<M, 0x13f, FK, DUMP>(a, O, B); break;
+            case 0x17f: bn = sl_node<M, 0x17f, FK, DUMP>(a, O, B); break;
+            case 0x1ff: bn = sl_node<M, 0x1ff, FK, DUMP>(a, O, B); break;
+            case 0x33f: bn = sl_node<M, 0x33f, FK, DUMP>(a, O, B); break;
+            case 0x37f: bn = sl_node<M, 0x37f, FK, DUMP>(a, O, B); break;
+            case 0x3ff: bn = sl_node<M, 0x3ff, FK, DUMP>(a, O, B); break;
+            case 0x77f: bn = sl_node<M, 0x77f, FK, DUMP>(a, O, B); break;
+            case 0x7ff: bn = sl_node<M, 0x7ff, FK, DUMP>(a, O, B); break;
+            case 0xfff: bn = sl_node<M, 0xfff, FK, DUMP>(a, O, B); break;
+            case 0x177f: bn = sl_node<M, 0x177f, FK, DUMP>(a, O, B); break;
+            case 0x17ff: bn = sl_node<M, 0x17ff, FK, DUMP>(a, O, B); break;
+            case 0x1fff: bn = sl_node<M, 0x1fff, FK, DUMP>(a, O, B); break;
+            case 0x3fff: bn = sl_node<M, 0x3fff, FK, DUMP>(a, O, B); break;
+            case 0x7fff: bn = sl_node<M, 0x7fff, FK, DUMP>(a, O, B); break;
+            case 0xffff: bn = sl_node<M, 0xffff, FK, DUMP>(a, O, B); break;
             default:
                 blk_generic<M, FK, true, DUMP>(a, O, B);
                 bn = B.beta;
@@ -464,16 +474,16 @@ __device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
         }
     } else {
         switch (p) {
-            case 0x0: bn = sl_node<M, 0x0, FK, DUMP>(a, O, bn, B); break;
-            case 0x1: bn = sl_node<M, 0x1, FK, DUMP>(a, O, bn, B); break;
-            case 0x3: bn = sl_node<M, 0x3, FK, DUMP>(a, O, bn, B); break;
-            case 0x7: bn = sl_node<M, 0x7, FK, DUMP>(a, O, bn, B); break;
-            case 0xf: bn = sl_node<M, 0xf, FK, DUMP>(a, O, bn, B); break;
-            case 0x17: bn = sl_node<M, 0x17, FK, DUMP>(a, O, bn, B); break;
-            case 0x1f: bn = sl_node<M, 0x1f, FK, DUMP>(a, O, bn, B); break;
-            case 0x3f: bn = sl_node<M, 0x3f, FK, DUMP>(a, O, bn, B); break;
-            case 0x7f: bn = sl_node<M, 0x7f, FK, DUMP>(a, O, bn, B); break;
-            case 0xff: bn = sl_node<M, 0xff, FK, DUMP>(a, O, bn, B); break;
+            case 0x0: bn = sl_node<M, 0x0, FK, DUMP>(a, O, B); break;
+            case 0x1: bn = sl_node<M, 0x1, FK, DUMP>(a, O, B); break;
+            case 0x3: bn = sl_node<M, 0x3, FK, DUMP>(a, O, B); break;
+            case 0x7: bn = sl_node<M, 0x7, FK, DUMP>(a, O, B); break;
+            case 0xf: bn = sl_node<M, 0xf, FK, DUMP>(a, O, B); break;
+            case 0x17: bn = sl_node<M, 0x17, FK, DUMP>(a, O, B); break;
+            case 0x1f: bn = sl_node<M, 0x1f, FK, DUMP>(a, O, B); break;
+            case 0x3f: bn = sl_node<M, 0x3f, FK, DUMP>(a, O, B); break;
+            case 0x7f: bn = sl_node<M, 0x7f, FK, DUMP>(a, O, B); break;
+            case 0xff: bn = sl_node<M, 0xff, FK, DUMP>(a, O, B); break;
             default:
                 blk_generic<M, FK, true, DUMP>(a, O, B);
                 bn = B.beta;
