@@ -434,7 +434,7 @@ __device__ __forceinline__ void blk_generic(float a, int O, Blk& B);
 // Size-SPEC_M node: straight-line code for each closed pattern (10 of 8
 // leaves, 27 of 16 leaves).
 template <int FK, bool DUMP>
-__device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
+__device__ __forceinline__ uint32_t spec_local(float a, int O, Blk& B) {
     constexpr int M = SPEC_M;
     const uint32_t p = (uint32_t)(B.F >> O) & ones32<M>();
     uint32_t bn;
@@ -490,7 +490,13 @@ __device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
                 break;
         }
     }
-    B.beta = sel_lanes(ones64(M) << O, bn, B.beta);
+    return bn;
+}
+
+template <int FK, bool DUMP>
+__device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
+    const uint32_t bn = spec_local<FK, DUMP>(a, O, B);
+    B.beta = sel_lanes(ones64(SPEC_M) << O, bn, B.beta);
 }
 
 // Node of size M at lane offset O (runtime).  Each size has one copy of its
@@ -677,6 +683,67 @@ struct SubIO {
     uint64_t* beta_out;        // lane-packed partial sums (out) or null
 };
 
+// State of one subtree decode shared by its node visits.
+struct SubCtx {
+    uint64_t mw, vw;  // lane l: frozen mask / values of block l
+    uint64_t A0, A1;  // bit b: block b is all frozen / has no frozen leaf
+    uint64_t vT;      // lane l, bit k: frozen value of leaf k*64 + l
+    uint64_t acc;     // lane-packed partial sums, bit k = element k*64 + lane
+};
+
+// One 64-leaf block (level 6 of the subtree): its LLRs are v.a6.
+template <int C, int FK, bool PRUNE, bool DUMP>
+__device__ __forceinline__ void sub_block(Lv<C>& v, SubCtx& x, const SubIO& io, int b) {
+    if (PRUNE && ((x.A0 >> b) & 1ull)) {
+        // rate 0: the block's frozen values re-encoded across the lanes
+        x.acc |= (lane_transform(x.vT >> b) & 1ull) << b;
+    } else {
+        Blk B;
+        blk_init(B, readlane64(x.mw, b), readlane64(x.vw, b));
+        blk_node<64, FK, PRUNE, DUMP>(v.a6, 0, B);
+        x.acc |= (uint64_t)(B.beta >> 31) << b;
+        if (DUMP && B.has_leaf) io.leaf[b * 64 + lane_id()] = B.leaf;
+    }
+}
+
+// Node of 2^L leaves (L >= 7) covering blocks [b, b + 2^(L-6)); its LLRs are
+// level L of v.  Each level has one copy of its code (the two children are
+// visited by a rolled loop, and a subtree smaller than 2^C passes through
+// the levels above its root), and every level keeps its LLRs in its own
+// registers or LDS area.
+template <int L, int C, int FK, bool PRUNE, bool DUMP>
+__device__ __forceinline__ void sub_node(Lv<C>& v, SubCtx& x, const SubIO& io, int b, int lg) {
+    constexpr int EB = 1 << (L - 6);  // blocks covered
+    constexpr int EH = EB / 2;        // blocks per child
+    const bool above = L > lg;        // above the subtree's root: pass through
+    bool done = above;
+    if (!above) {
+        const uint64_t rng = ones64(EB) << b;
+        if (PRUNE && (x.A0 & rng) == rng) {
+            // rate 0: beta = v G over the node, lane-packed
+            uint64_t w = (x.vT >> b) & ones64(EB);
+            w = word_transform(w, EB);
+            x.acc |= lane_transform(w) << b;
+            done = true;
+        } else if (PRUNE && (x.A1 & rng) == rng) {
+            uint64_t bits = 0;
+            done = level_rate1<L, C, FK>(v, bits);
+            if (done) x.acc |= bits << b;
+        }
+    }
+    if (above || !done) {
+        const int sides = above ? 1 : 2;
+#pragma clang loop unroll(disable)
+        for (int side = 0; side < sides; ++side) {
+            const int bc = b + side * EH;
+            if (!above) level_step<L - 1, C, FK>(v, side ? OP_G : OP_F, bc, x.acc);
+            if constexpr (L - 1 == 6) sub_block<C, FK, PRUNE, DUMP>(v, x, io, bc);
+            else sub_node<L - 1, C, FK, PRUNE, DUMP>(v, x, io, bc, lg);
+        }
+        if (!above) x.acc ^= (x.acc >> EH) & (ones64(EH) << b);  // beta = [beta_L ^ beta_R, beta_R]
+    }
+}
+
 // Decode a subtree of 2^lg leaves, 6 <= lg <= C, on one wavefront.  Input
 // LLRs: at lds + SubCfg<C>::off(lg) when lg > R, else at gsrc (global).
 template <int C, int FK, bool PRUNE, bool DUMP>
@@ -687,16 +754,19 @@ __device__ __forceinline__ void subtree_decode(const SubIO io, int lg, float* ld
     Lv<C> v;
     v.lds = lds;
 
+    SubCtx x;
     // Block words: lane l holds block l's mask and values.
-    uint64_t mw = 0, vw = 0;
+    x.mw = 0;
+    x.vw = 0;
     if (l < nb) {
-        mw = (uint64_t)io.mask[2 * l] | ((uint64_t)io.mask[2 * l + 1] << 32);
-        vw = (uint64_t)io.vals[2 * l] | ((uint64_t)io.vals[2 * l + 1] << 32);
+        x.mw = (uint64_t)io.mask[2 * l] | ((uint64_t)io.mask[2 * l + 1] << 32);
+        x.vw = (uint64_t)io.vals[2 * l] | ((uint64_t)io.vals[2 * l + 1] << 32);
     }
-    const uint64_t A0 = ballot(l < nb && mw == ~0ull);  // all-frozen blocks
-    const uint64_t A1 = ballot(l < nb && mw == 0ull);   // frozen-free blocks
-    uint64_t vT = 0;                                    // lane l, bit k = value of leaf k*64 + l
-    if (PRUNE && A0 != 0) vT = transpose64(vw);
+    x.A0 = ballot(l < nb && x.mw == ~0ull);  // all-frozen blocks
+    x.A1 = ballot(l < nb && x.mw == 0ull);   // frozen-free blocks
+    x.vT = 0;                                // lane l, bit k = value of leaf k*64 + l
+    if (PRUNE && x.A0 != 0) x.vT = transpose64(x.vw);
+    x.acc = 0;
 
     if (lg <= R) {
         switch (lg) {
@@ -706,84 +776,8 @@ __device__ __forceinline__ void subtree_decode(const SubIO io, int lg, float* ld
             default: v.a6 = gsrc[l]; break;
         }
     }
-
-    uint64_t acc = 0;
-    int b = 0;
-    int le = lg;
-    int op = OP_NONE;
-    while (true) {
-        int L = le;
-        int lc;
-        while (true) {
-            const int eb = 1 << (L - 6);
-            const uint64_t rng = ones64(eb) << b;
-            if (PRUNE && (A0 & rng) == rng) {
-                // rate 0: beta = v G over the node, lane-packed
-                uint64_t x = (vT >> b) & ones64(eb);
-                x = word_transform(x, eb);
-                x = lane_transform(x);
-                acc |= x << b;
-                lc = L;
-                break;
-            }
-            if (L == 6) {
-                if (op == OP_F) {
-                    v.a6 = fupd<FK>(v.a7[0], v.a7[1]);
-                } else if (op == OP_G) {
-                    const uint32_t sgn = (uint32_t)((acc >> (b - 1)) & 1ull) << 31;
-                    v.a6 = gupd(v.a7[0], v.a7[1], sgn);
-                }
-                Blk B;
-                blk_init(B, readlane64(mw, b), readlane64(vw, b));
-                blk_node<64, FK, PRUNE, DUMP>(v.a6, 0, B);
-                acc |= (uint64_t)(B.beta >> 31) << b;
-                if (DUMP && B.has_leaf) io.leaf[b * 64 + l] = B.leaf;
-                lc = 6;
-                break;
-            }
-            if (op != OP_NONE) {
-                switch (L) {
-                    case 11: if constexpr (C >= 12) level_step<11, C, FK>(v, op, b, acc); break;
-                    case 10: if constexpr (C >= 11) level_step<10, C, FK>(v, op, b, acc); break;
-                    case 9: if constexpr (C >= 10) level_step<9, C, FK>(v, op, b, acc); break;
-                    case 8: if constexpr (C >= 9) level_step<8, C, FK>(v, op, b, acc); break;
-                    case 7: if constexpr (C >= 8) level_step<7, C, FK>(v, op, b, acc); break;
-                }
-            }
-            uint64_t bits = 0;
-            bool ok = false;
-            if (PRUNE && (A1 & rng) == rng) {
-                switch (L) {
-                    case 12: if constexpr (C >= 12) ok = level_rate1<12, C, FK>(v, bits); break;
-                    case 11: if constexpr (C >= 11) ok = level_rate1<11, C, FK>(v, bits); break;
-                    case 10: if constexpr (C >= 10) ok = level_rate1<10, C, FK>(v, bits); break;
-                    case 9: if constexpr (C >= 9) ok = level_rate1<9, C, FK>(v, bits); break;
-                    case 8: if constexpr (C >= 8) ok = level_rate1<8, C, FK>(v, bits); break;
-                    case 7: ok = level_rate1<7, C, FK>(v, bits); break;
-                }
-            }
-            if (ok) {
-                acc |= bits << b;
-                lc = L;
-                break;
-            }
-            --L;
-            op = OP_F;
-        }
-        // The node at level lc covering blocks [b, b + 2^(lc-6)) is complete.
-        // Every ancestor whose right child has just completed combines its
-        // halves; past the last block that is the whole right spine.
-        b += 1 << (lc - 6);
-        const int top = (b >= nb) ? lg : 6 + __builtin_ctz((unsigned)b);
-        for (int lp = lc + 1; lp <= top; ++lp) {
-            const int e = 1 << (lp - 7);  // blocks per child of the level-lp node
-            const int b0 = b - 2 * e;
-            acc ^= (acc >> e) & (ones64(e) << b0);
-        }
-        if (b >= nb) break;
-        le = top;
-        op = OP_G;
-    }
+    sub_node<C, C, FK, PRUNE, DUMP>(v, x, io, 0, lg);
+    const uint64_t acc = x.acc;
 
     if (io.beta_out) io.beta_out[l] = acc;
 

@@ -205,7 +205,7 @@ def closed_patterns(m):
 
 def _kernel_cases():
     src = open(SRC).read()
-    body = src[src.index("__device__ __forceinline__ void blk_spec"):]
+    body = src[src.index("__device__ __forceinline__ uint32_t spec_local"):]
     body = body[: body.index("\n}\n")]
     m16, m8 = body.split("} else {", 1)
     grab = lambda t: sorted(int(x, 16) for x in re.findall(r"case (0x[0-9a-f]+):", t))
