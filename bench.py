@@ -39,6 +39,39 @@ if ROOT not in sys.path:
 import synth  # noqa: E402
 
 METRIC = "decoded Mbit/s @N=2^20 SC (batched vs plain, 1 GPU); serving p50/p99 latency"
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def decoder_source_hash() -> str:
+    """Hash of what defines the min-sum decode kernel (its sources and the
+    device compile flags): HBM traffic measured with counters is reported only
+    for the kernel it was measured on."""
+    import hashlib
+
+    from paper_1204_5882_amd import build as pb
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1204_5882_amd", "csrc")
+    for rel in ("sc_kernels.h", "sc_device.h", os.path.join("variants", "dec_c12_ms_prune.hip")):
+        with open(os.path.join(csrc, rel), "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(pb.COMMON[:-2] + pb.DEVICE_ONLY).encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cfg_name: str, source: str):
+    """HBM bytes per decode launch from the committed counter summary of this
+    workload (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known
+    size), or None when the summary was taken on another kernel."""
+    path = os.path.join(PROFILES, f"hbm_traffic_{cfg_name}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic: "):
+            rec = json.loads(line[len("traffic: "):])
+            if rec.get("source") == source:
+                return rec
+    return None
 HBM_PEAK_GBS = 8000.0
 CUTOVER_FOR_MODEL = 12
 
@@ -351,8 +384,12 @@ def main(argv=None):
     # roofline of the decode kernel: algorithmic bytes / measured launch time
     alg_bytes = sum((1 << it["log2n"]) * bytes_per_bit(it["log2n"]) for it in items)
     achieved = alg_bytes / (ev_ms / 1e3) / 1e9
+    source = decoder_source_hash()
+    tr = measured_traffic(args.config, source) if (cfg["fkind"] == 0 and args.prune and not args.cutover) else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None if tr is None else int(tr["bytes"]))
+    if tr is not None:
+        roof["traffic_over_algorithmic"] = round(tr["bytes"] / alg_bytes, 3)
 
     # correctness spot check of the timed output against the oracle (CPU leg)
     out = dict(metric=METRIC, value=round(value, 1), unit="Mbit/s", n_gpus=1, steps=args.steps,
@@ -361,7 +398,7 @@ def main(argv=None):
                config=dict(workload=f"{args.config}: {cfg['desc']}", frames=n,
                            bits_per_step=total_bits, info_bits_per_step=info_bits,
                            f_kind="boxplus" if cfg["fkind"] else "minsum", prune=bool(args.prune),
-                           graph=bool(args.graph),
+                           graph=bool(args.graph), decoder_source=source,
                            launch=ctx.query_launch(cfg["fkind"], max(it["log2n"] for it in items), n)),
                roofline=roof,
                kernel_ms_mean=round(ev_ms, 3), kernel_ms_min=round(float(np.min(per)), 3),
