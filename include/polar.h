@@ -120,8 +120,7 @@ typedef struct polar_ctx polar_ctx;
                                    10, 11 or 12; 0 = automatic (default: the tuned
                                    value, else 12).  Leaf-LLR dumps and unpruned
                                    decoding always use 12.                                */
-#define POLAR_OPT_WG_WAVES 3    /* wavefronts per workgroup: 4 or 8; 0 = automatic.
-                                   Pruned box-plus decoding runs with at most 4.        */
+#define POLAR_OPT_WG_WAVES 3    /* wavefronts per workgroup: 4 or 8; 0 = automatic (8) */
 #define POLAR_OPT_MAX_SLOTS 4   /* max frames in flight (workgroups); 0 = automatic
                                    (the tuned value, else 2 per compute unit)           */
 #define POLAR_OPT_TIMING 5      /* device pointer (as an integer) to 8 zeroed uint64

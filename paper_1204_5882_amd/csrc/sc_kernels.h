@@ -1026,16 +1026,14 @@ static __global__ void k_reset_counter(unsigned* counter) {
     if (threadIdx.x == 0) counter[0] = 0u;
 }
 
-// Pruned box-plus decoding needs more than the 256 registers a lane may use
-// in an 8-wavefront workgroup, so it runs with at most 4 wavefronts.
-template <int FK, bool PRUNE>
-constexpr int max_waves() { return (FK == 1 && PRUNE) ? 4 : 8; }
+// Every variant fits the register budget of 8 wavefronts per workgroup.
+constexpr int MAX_WAVES = 8;
 
 template <int C, int FK, bool PRUNE, bool DUMP>
 hipError_t launch_decode(const DecodeLaunch& a) {
-    constexpr int MAXW = max_waves<FK, PRUNE>();
-    if (a.waves < 1) return hipErrorInvalidValue;
-    const int waves = a.waves < MAXW ? a.waves : MAXW;
+    constexpr int MAXW = MAX_WAVES;
+    if (a.waves < 1 || a.waves > MAXW) return hipErrorInvalidValue;
+    const int waves = a.waves;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, a.stream, a.counter);
     hipLaunchKernelGGL((k_sc_decode<C, FK, PRUNE, DUMP, MAXW>), dim3(a.grid), dim3(waves * 64), 0, a.stream,
                        a.descs, a.n_frames, a.counter, a.slots, a.slot_bytes, a.prof);
