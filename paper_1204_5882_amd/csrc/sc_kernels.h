@@ -290,9 +290,6 @@ constexpr int ilog2() { return M <= 1 ? 0 : 1 + ilog2<M / 2>(); }
 struct Blk {
     uint64_t F;       // frozen mask of the block (bit i = leaf i), wave-uniform
     uint64_t V;       // frozen values of the block (zero outside F), wave-uniform
-    uint64_t TA[7];   // node types per level L (size 2^L), bit O for the node at
-    uint64_t TB[7];   // offset O: type = TA + 2 TB (0 mixed, 1 rate 0,
-                      // 2 rate 1, 3 repetition)
     uint32_t fv;      // lane i: SIGN if leaf i is frozen with value 1
     uint32_t w[7];    // lane i: SIGN if bit i of the frozen values re-encoded
                       // inside every aligned 2^t-block (w[0] = fv)
@@ -534,7 +531,9 @@ __device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
         if constexpr (PRUNE) {
             neg = ballot(a < 0.0f);
             low = ballot(below_rate1_floor<FK, LG>(a));
-            type = (int)((B.TA[LG] >> O) & 1ull) | ((int)((B.TB[LG] >> O) & 1ull) << 1);
+            // node type from its frozen pattern: 1 rate 0, 2 rate 1, 3 repetition
+            const uint64_t fm = (B.F >> O) & ones64(M);
+            type = fm == ones64(M) ? 1 : fm == 0 ? 2 : fm == (ones64(M) >> 1) ? 3 : 0;
             // rate-1 node with an LLR at or under the floor (an exact zero
             // under min-sum): hard decisions need not be SC there, decode it
             if (type == 2 && (low & (ones64(M) << O)) != 0) type = 0;
@@ -568,19 +567,12 @@ __device__ __forceinline__ void blk_init(Blk& B, uint64_t F, uint64_t V) {
     B.V = V & F;
     uint64_t W = V & F;
     B.w[0] = lane_bit(W) ? SIGN : 0u;
-    uint64_t r0 = F, r1 = ~F, rp = ~F;  // size 1: rate 0 = frozen, rate 1 = repetition = information
 #pragma unroll
     for (int t = 1; t < 7; ++t) {
         const int h = 1 << (t - 1);
         W ^= (W >> h) & low_mask64(h);
         B.w[t] = lane_bit(W) ? SIGN : 0u;
-        rp = r0 & (rp >> h);  // left half rate 0, right half repetition
-        r0 = r0 & (r0 >> h);
-        r1 = r1 & (r1 >> h);
-        B.TA[t] = r0 | rp;
-        B.TB[t] = r1 | rp;
     }
-    B.TA[0] = B.TB[0] = 0;
     B.fv = B.w[0];
     B.beta = 0;
     B.leaf = 0.0f;
