@@ -815,6 +815,21 @@ __device__ __forceinline__ void tiny_decode(const FrameDesc& fd) {
 constexpr int SWEEP_UNROLL = 8;  // rows in flight per wave
 
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+// The sweeps sit in the same loop as the register-hungry leaf decoder: their
+// per-lane offsets, if hoisted out of that loop, would stay live across it
+// and force spills.  An empty volatile asm makes the lane index and the first
+// row opaque at every call, so the offsets are recomputed where used.
+__device__ __forceinline__ int lane_id_here() {
+    int x = lane_id();
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ int64_t row_here(int wave) {
+    int r = __builtin_amdgcn_readfirstlane(wave);
+    asm volatile("" : "+s"(r));
+    return r;
+}
 __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
 
 template <int FK>
@@ -825,9 +840,9 @@ __device__ __forceinline__ float4 f4(float4 a, float4 b) {
 template <int FK>
 __device__ __forceinline__ void sweep_f(const float* __restrict__ in, int64_t half, float* __restrict__ out,
                                         int wave, int nw) {
-    const int l4 = lane_id() * 4;
+    const int l4 = lane_id_here() * 4;
     const int64_t rows = half >> 8;
-    int64_t r = wave;
+    int64_t r = row_here(wave);
     for (; r + (SWEEP_UNROLL - 1) * nw < rows; r += SWEEP_UNROLL * nw) {
         float4 x[SWEEP_UNROLL], y[SWEEP_UNROLL];
 #pragma unroll
@@ -865,9 +880,9 @@ template <int C>
 __device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t half,
                                         const uint64_t* __restrict__ beta, float* __restrict__ out,
                                         int wave, int nw) {
-    const int l4 = lane_id() * 4;
+    const int l4 = lane_id_here() * 4;
     const int64_t rows = half >> 8;
-    int64_t r = wave;
+    int64_t r = row_here(wave);
     for (; r + (SWEEP_UNROLL - 1) * nw < rows; r += SWEEP_UNROLL * nw) {
         float4 x[SWEEP_UNROLL], y[SWEEP_UNROLL];
 #pragma unroll
@@ -885,6 +900,53 @@ __device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t ha
     for (; r < rows; r += nw) {
         const int64_t j = r * 256 + l4;
         st4(out + j, g4<C>(ld4(in + j), ld4(in + j + half), beta, j));
+    }
+}
+
+// Two levels in one pass.  The first level (f, or g with partial sums beta)
+// maps in[0 .. 2h) to mid[0 .. h); the second (f) maps mid to out[0 .. h/2).
+// Each lane takes elements j .. j+3 of out and produces mid[j], mid[j + h/2]
+// (and their 4-wide neighbours) from in[j], in[j + h], in[j + h/2],
+// in[j + h/2 + h]: mid is written for its later g but not read back.
+template <int C, int FK, bool G>
+__device__ __forceinline__ void sweep2(const float* __restrict__ in, int64_t h, const uint64_t* __restrict__ beta,
+                                       float* __restrict__ mid, float* __restrict__ out, int wave, int nw) {
+    constexpr int U = SWEEP_UNROLL / 4;
+    const int l4 = lane_id_here() * 4;
+    const int64_t q = h >> 1;
+    const int64_t rows = q >> 8;
+    const auto first = [&](float4 a, float4 b, int64_t j) -> float4 {
+        if constexpr (G) return g4<C>(a, b, beta, j);
+        else return f4<FK>(a, b);
+    };
+    int64_t r = row_here(wave);
+    for (; r + (U - 1) * nw < rows; r += U * nw) {
+        float4 a0[U], b0[U], a1[U], b1[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const int64_t j = (r + i * nw) * 256 + l4;
+            a0[i] = ld4(in + j);
+            b0[i] = ld4(in + j + h);
+            a1[i] = ld4(in + j + q);
+            b1[i] = ld4(in + j + q + h);
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const int64_t j = (r + i * nw) * 256 + l4;
+            const float4 m0 = first(a0[i], b0[i], j);
+            const float4 m1 = first(a1[i], b1[i], j + q);
+            st4(mid + j, m0);
+            st4(mid + j + q, m1);
+            st4(out + j, f4<FK>(m0, m1));
+        }
+    }
+    for (; r < rows; r += nw) {
+        const int64_t j = r * 256 + l4;
+        const float4 m0 = first(ld4(in + j), ld4(in + j + h), j);
+        const float4 m1 = first(ld4(in + j + q), ld4(in + j + q + h), j + q);
+        st4(mid + j, m0);
+        st4(mid + j + q, m1);
+        st4(out + j, f4<FK>(m0, m1));
     }
 }
 
@@ -910,7 +972,7 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
     const int W = (int)(blockDim.x >> 6);  // wavefronts in the workgroup
     constexpr int R = SubCfg<C>::R;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps sweep offsets scalar
     const int n = fd.log2n;
     if (n < 6) {
         if (wave == 0) tiny_decode<FK, PRUNE, DUMP>(fd);
@@ -954,18 +1016,27 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
                 combine_words(beta + (s - (1ll << q)) * 64, (1ll << (q - 1)) * 64, tid, W * 64);
                 __syncthreads();
             }
-            // g: parent at depth D - t - 1, right child at depth D - t
+            // g: parent at depth D - t - 1, right child at depth D - t; when
+            // the f chain continues, the first f rides in the same pass
             const int dp = D - t - 1;
             const int64_t half = N >> (dp + 1);
-            float* dst = (t == 0) ? lds : level(D - t);
-            sweep_g<C>(level(dp), half, beta + (s - (1ll << t)) * 64, dst, wave, W);
+            const uint64_t* bl = beta + (s - (1ll << t)) * 64;
+            if (t == 0) {
+                sweep_g<C>(level(dp), half, bl, lds, wave, W);
+            } else {
+                sweep2<C, FK, true>(level(dp), half, bl, level(D - t), t == 1 ? lds : level(D - t + 1), wave, W);
+            }
             __syncthreads();
         }
-        // f chain down to the cutover depth (the cutover node goes to LDS)
-        for (int d = D - t + 1; d <= D; ++d) {
-            const int64_t half = N >> d;
-            float* dst = (d == D) ? lds : level(d);
-            sweep_f<FK>(level(d - 1), half, dst, wave, W);
+        // rest of the f chain down to the cutover depth (the cutover node goes
+        // to LDS), two levels per pass
+        int d = (s == 0) ? 1 : D - t + 2;
+        for (; d + 1 <= D; d += 2) {
+            sweep2<C, FK, false>(level(d - 1), N >> d, nullptr, level(d), d + 1 == D ? lds : level(d + 1), wave, W);
+            __syncthreads();
+        }
+        if (d == D) {
+            sweep_f<FK>(level(d - 1), N >> d, lds, wave, W);
             __syncthreads();
         }
         if (wave == 0) {
