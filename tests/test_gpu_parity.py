@@ -294,3 +294,47 @@ def test_cfg3_n2p24_boxplus_sampled():
     us, leaves = decode(frames, f_kind=1, prune=False, dump=True)
     rescued = _check_boxplus(frames, us, leaves)
     print(f"cfg3: {rescued} leaves within tolerance only through S_i")
+
+
+# ---------------------------------------------------------------- mixed workload
+def _oracle_threads(frames, boxplus=False):
+    """Oracle u-hat for frames of mixed sizes, one frame per host thread (the
+    oracle runs in C without the interpreter lock)."""
+    import concurrent.futures as cf
+    import os
+
+    n = max(1, min(16, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(n) as ex:
+        return list(ex.map(lambda f: oracle.sc_decode(f[0], f[1], f[2], boxplus=boxplus)[0], frames))
+
+
+@pytest.mark.timeout(600)
+def test_mixed_512_frames_full_size():
+    """The mixed workload at full size in the launch configuration the
+    benchmark uses: 512 frames, log2 N uniform on 16..22, half BSC (p in
+    [0.01, 0.05]) and half BIAWGN (sigma in [0.8, 1.2]), union-bound rates,
+    one mask per (N, channel), min-sum, shuffled.  Every frame's u-hat must
+    equal the oracle's."""
+    g = np.random.default_rng(512)
+    ps = [0.01, 0.02, 0.035, 0.05]
+    sigmas = [0.8, 0.93, 1.07, 1.2]
+    specs = []
+    for f in range(512):
+        log2n = int(g.integers(16, 23))
+        specs.append((log2n, "bsc", ps[int(g.integers(0, 4))]) if f < 256 else
+                     (log2n, "biawgn", sigmas[int(g.integers(0, 4))]))
+    specs = [specs[i] for i in g.permutation(512)]
+    masks = {}
+    frames = []
+    for k, (log2n, ch, prm) in enumerate(specs):
+        key = (log2n, ch, prm)
+        if key not in masks:
+            z0 = synth.bsc_z0(prm) if ch == "bsc" else synth.biawgn_z0(prm)
+            masks[key] = oracle.frozen_set(log2n, z0, -1, 0.1)[0]
+        _, fval, llr = synth.frame(60000 + k, log2n, ch, prm, masks[key], lambda v, n=log2n: oracle.encode(n, v))
+        frames.append((llr, masks[key], fval))
+    _say(f"case: mixed 512 frames, {sum(f[0].size for f in frames) / 1e6:.0f} Mbit, {len(masks)} masks")
+    us, _ = decode(frames, prune=True)
+    refs = _oracle_threads(frames)
+    bad = [k for k, (u, r) in enumerate(zip(us, refs)) if not np.array_equal(u, r)]
+    assert not bad, f"frames differing from the oracle: {bad[:10]}"
