@@ -436,38 +436,50 @@ __device__ __forceinline__ uint32_t spec_local(float a, int O, Blk& B) {
     const uint32_t p = (uint32_t)(B.F >> O) & ones32<M>();
     uint32_t bn;
     if constexpr (M == 16) {
+        // Two levels: the five patterns that make up over 90% of the 16-leaf
+        // nodes of Bhattacharyya-built codes first, then the rest.  The
+        // selector of the second switch is made opaque so that the compiler
+        // does not fold both into one deeper branch tree (a data-dependent
+        // multiway branch is a chain of scalar tests and taken branches).
         switch (p) {
-            case 0x0: bn = sl_node<M, 0x0, FK, DUMP>(a, O, B); break;
-            case 0x1: bn = sl_node<M, 0x1, FK, DUMP>(a, O, B); break;
-            case 0x3: bn = sl_node<M, 0x3, FK, DUMP>(a, O, B); break;
-            case 0x7: bn = sl_node<M, 0x7, FK, DUMP>(a, O, B); break;
-            case 0xf: bn = sl_node<M, 0xf, FK, DUMP>(a, O, B); break;
-            case 0x17: bn = sl_node<M, 0x17, FK, DUMP>(a, O, B); break;
-            case 0x1f: bn = sl_node<M, 0x1f, FK, DUMP>(a, O, B); break;
-            case 0x3f: bn = sl_node<M, 0x3f, FK, DUMP>(a, O, B); break;
-            case 0x7f: bn = sl_node<M, 0x7f, FK, DUMP>(a, O, B); break;
-            case 0xff: bn = sl_node<M, 0xff, FK, DUMP>(a, O, B); break;
-            case 0x117: bn = sl_node<M, 0x117, FK, DUMP>(a, O, B); break;
-            case 0x11f: bn = sl_node<M, 0x11f, FK, DUMP>(a, O, B); break;
-            case 0x13f: bn = sl_node<M, 0x13f, FK, DUMP>(a, O, B); break;
-            case 0x17f: bn = sl_node<M, 0x17f, FK, DUMP>(a, O, B); break;
-            case 0x1ff: bn = sl_node<M, 0x1ff, FK, DUMP>(a, O, B); break;
-            case 0x33f: bn = sl_node<M, 0x33f, FK, DUMP>(a, O, B); break;
-            case 0x37f: bn = sl_node<M, 0x37f, FK, DUMP>(a, O, B); break;
-            case 0x3ff: bn = sl_node<M, 0x3ff, FK, DUMP>(a, O, B); break;
-            case 0x77f: bn = sl_node<M, 0x77f, FK, DUMP>(a, O, B); break;
-            case 0x7ff: bn = sl_node<M, 0x7ff, FK, DUMP>(a, O, B); break;
-            case 0xfff: bn = sl_node<M, 0xfff, FK, DUMP>(a, O, B); break;
             case 0x177f: bn = sl_node<M, 0x177f, FK, DUMP>(a, O, B); break;
-            case 0x17ff: bn = sl_node<M, 0x17ff, FK, DUMP>(a, O, B); break;
-            case 0x1fff: bn = sl_node<M, 0x1fff, FK, DUMP>(a, O, B); break;
-            case 0x3fff: bn = sl_node<M, 0x3fff, FK, DUMP>(a, O, B); break;
+            case 0x117: bn = sl_node<M, 0x117, FK, DUMP>(a, O, B); break;
+            case 0x1: bn = sl_node<M, 0x1, FK, DUMP>(a, O, B); break;
             case 0x7fff: bn = sl_node<M, 0x7fff, FK, DUMP>(a, O, B); break;
-            case 0xffff: bn = sl_node<M, 0xffff, FK, DUMP>(a, O, B); break;
-            default:
-                blk_generic<M, FK, true, DUMP>(a, O, B);
-                bn = B.beta;
+            case 0x0: bn = sl_node<M, 0x0, FK, DUMP>(a, O, B); break;
+            default: {
+                uint32_t q = __builtin_amdgcn_readfirstlane(p);
+                asm volatile("" : "+s"(q));
+                switch (q) {
+                    case 0x3: bn = sl_node<M, 0x3, FK, DUMP>(a, O, B); break;
+                    case 0x7: bn = sl_node<M, 0x7, FK, DUMP>(a, O, B); break;
+                    case 0xf: bn = sl_node<M, 0xf, FK, DUMP>(a, O, B); break;
+                    case 0x17: bn = sl_node<M, 0x17, FK, DUMP>(a, O, B); break;
+                    case 0x1f: bn = sl_node<M, 0x1f, FK, DUMP>(a, O, B); break;
+                    case 0x3f: bn = sl_node<M, 0x3f, FK, DUMP>(a, O, B); break;
+                    case 0x7f: bn = sl_node<M, 0x7f, FK, DUMP>(a, O, B); break;
+                    case 0xff: bn = sl_node<M, 0xff, FK, DUMP>(a, O, B); break;
+                    case 0x11f: bn = sl_node<M, 0x11f, FK, DUMP>(a, O, B); break;
+                    case 0x13f: bn = sl_node<M, 0x13f, FK, DUMP>(a, O, B); break;
+                    case 0x17f: bn = sl_node<M, 0x17f, FK, DUMP>(a, O, B); break;
+                    case 0x1ff: bn = sl_node<M, 0x1ff, FK, DUMP>(a, O, B); break;
+                    case 0x33f: bn = sl_node<M, 0x33f, FK, DUMP>(a, O, B); break;
+                    case 0x37f: bn = sl_node<M, 0x37f, FK, DUMP>(a, O, B); break;
+                    case 0x3ff: bn = sl_node<M, 0x3ff, FK, DUMP>(a, O, B); break;
+                    case 0x77f: bn = sl_node<M, 0x77f, FK, DUMP>(a, O, B); break;
+                    case 0x7ff: bn = sl_node<M, 0x7ff, FK, DUMP>(a, O, B); break;
+                    case 0xfff: bn = sl_node<M, 0xfff, FK, DUMP>(a, O, B); break;
+                    case 0x17ff: bn = sl_node<M, 0x17ff, FK, DUMP>(a, O, B); break;
+                    case 0x1fff: bn = sl_node<M, 0x1fff, FK, DUMP>(a, O, B); break;
+                    case 0x3fff: bn = sl_node<M, 0x3fff, FK, DUMP>(a, O, B); break;
+                    case 0xffff: bn = sl_node<M, 0xffff, FK, DUMP>(a, O, B); break;
+                    default:
+                        blk_generic<M, FK, true, DUMP>(a, O, B);
+                        bn = B.beta;
+                        break;
+                }
                 break;
+            }
         }
     } else {
         switch (p) {
@@ -496,9 +508,11 @@ __device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
     B.beta = sel_lanes(ones64(SPEC_M) << O, bn, B.beta);
 }
 
-// Node of size M at lane offset O (runtime).  Each size has one copy of its
-// code: the two children are visited by a two-pass loop that is kept rolled,
-// so the code grows with log M rather than with the number of nodes.
+// Node of size M at lane offset O (runtime), used at 32 and 64 leaves (and
+// for patterns outside the specialized set).  The two children are visited
+// by an unrolled two-pass loop: the pattern-specialized 16-leaf code is then
+// inlined four times per block, which measured faster than the rolled loop's
+// branches despite the larger code.
 //
 // Both ballots of a node are taken unconditionally at its top and only read
 // inside the shortcut branches: with a ballot placed under the rate-1 test
@@ -540,7 +554,7 @@ __device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
         }
         if (type == 0) {
             constexpr int H = M / 2;
-#pragma clang loop unroll(disable)
+#pragma unroll
             for (int side = 0; side < 2; ++side) {
                 float c;
                 if (side == 0) {
