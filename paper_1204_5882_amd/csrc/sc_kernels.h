@@ -388,9 +388,9 @@ constexpr uint64_t left_lanes() {
 // picks its halves with a constant lane mask.  Decisions stay in vector
 // registers except where a ballot is inherent (rate-1 zero test, repetition
 // decision).
-template <int M, uint32_t P, int FK, bool DUMP>
+template <int M, uint64_t P, int FK, bool DUMP>
 __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
-    constexpr uint32_t ALL = ones32<M>();
+    constexpr uint64_t ALL = ones64(M);
     constexpr int LG = ilog2<M>();
     if constexpr (P == ALL) {
         return B.w[LG];  // rate 0 (a frozen leaf: its revealed value)
@@ -401,8 +401,9 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
         }
         return (a < 0.0f) ? SIGN : 0u;
     } else if constexpr (P == 0 && FK == 0) {
-        const uint32_t S = (uint32_t)(ballot(a < 0.0f) >> O) & ALL;
-        const uint32_t Z = (uint32_t)(ballot(a == 0.0f) >> O) & ALL;
+        static_assert(M <= 32, "three-state words are 32 bits");
+        const uint32_t S = (uint32_t)((ballot(a < 0.0f) >> O) & ALL);
+        const uint32_t Z = (uint32_t)((ballot(a == 0.0f) >> O) & ALL);
         const uint64_t bits = (uint64_t)r1_bits<M>(S, Z) << O;
         return lane_bit(bits) ? SIGN : 0u;
     } else if constexpr (P == (ALL >> 1)) {
@@ -416,7 +417,7 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
         return B.w[LG] ^ (u << 31);
     } else {
         constexpr int H = M / 2;
-        constexpr uint32_t LO = ones32<H>();
+        constexpr uint64_t LO = ones64(H);
         const float c = fupd<FK>(a, lane_downf<H>(a));
         const uint32_t bl = sl_node<H, (P & LO), FK, DUMP>(c, O, B);
         const float d = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bl));
@@ -518,9 +519,42 @@ __device__ __forceinline__ void blk_spec(float a, int O, Blk& B) {
 // inside the shortcut branches: with a ballot placed under the rate-1 test
 // (or an early return nested in that test) this toolchain's -O2/-O3 code
 // returned corrupted partial sums after a failed test, exact at -O1.
+// The most frequent mixed 64- and 32-leaf patterns of Bhattacharyya-built
+// codes (each a composition of frequent 16-leaf patterns) get straight-line
+// code too: one dispatch replaces the generic node's type test and the
+// dispatches of its children.  Other patterns take the generic node.
 template <int M, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void blk_node(float a, int O, Blk& B) {
-    if constexpr (PRUNE && M == SPEC_M) {
+    // (64-leaf cases only for min-sum without the leaf dump: with box-plus's
+    // longer f, or the dump, they exceed the register budget)
+    if constexpr (PRUNE && M == 64 && FK == 0 && !DUMP) {
+        uint32_t bn;
+        bool known = true;
+        switch (B.F) {
+            case 0x177f7fff7fffffffull: bn = sl_node<64, 0x177f7fff7fffffffull, FK, DUMP>(a, 0, B); break;
+            case 0x0117177f177f7fffull: bn = sl_node<64, 0x0117177f177f7fffull, FK, DUMP>(a, 0, B); break;
+            case 0x000101170117177full: bn = sl_node<64, 0x000101170117177full, FK, DUMP>(a, 0, B); break;
+            case 0x0000000100010117ull: bn = sl_node<64, 0x0000000100010117ull, FK, DUMP>(a, 0, B); break;
+            case 0x0000000000000001ull: bn = sl_node<64, 0x0000000000000001ull, FK, DUMP>(a, 0, B); break;
+            default: known = false; bn = 0; break;
+        }
+        if (known) B.beta = bn;
+        else blk_generic<M, FK, PRUNE, DUMP>(a, O, B);
+    } else if constexpr (PRUNE && M == 32) {
+        uint32_t bn;
+        bool known = true;
+        switch ((uint32_t)(B.F >> O)) {
+            case 0x177f7fffu: bn = sl_node<32, 0x177f7fffu, FK, DUMP>(a, O, B); break;
+            case 0x0117177fu: bn = sl_node<32, 0x0117177fu, FK, DUMP>(a, O, B); break;
+            case 0x00010117u: bn = sl_node<32, 0x00010117u, FK, DUMP>(a, O, B); break;
+            case 0x00000001u: bn = sl_node<32, 0x00000001u, FK, DUMP>(a, O, B); break;
+            case 0x7fffffffu: bn = sl_node<32, 0x7fffffffu, FK, DUMP>(a, O, B); break;
+            case 0xffffffffu: bn = sl_node<32, 0xffffffffu, FK, DUMP>(a, O, B); break;
+            default: known = false; bn = 0; break;
+        }
+        if (known) B.beta = sel_lanes(ones64(32) << O, bn, B.beta);
+        else blk_generic<M, FK, PRUNE, DUMP>(a, O, B);
+    } else if constexpr (PRUNE && M == SPEC_M) {
         blk_spec<FK, DUMP>(a, O, B);
     } else {
         blk_generic<M, FK, PRUNE, DUMP>(a, O, B);

@@ -235,3 +235,40 @@ def test_every_aligned_node_of_real_codes_is_closed(log2n, z0, n_frozen):
         rows = mask.reshape(-1, 1 << m).astype(np.uint64)
         pats = (rows << np.arange(1 << m, dtype=np.uint64)).sum(axis=1)
         assert set(int(p) for p in np.unique(pats)) <= closed
+
+
+def _is_closed(F, m):
+    size = 1 << m
+    return all((F >> i) & 1 for j in range(size) if (F >> j) & 1 for i in _weaker(j, m))
+
+
+def test_hot_32_and_64_leaf_cases_are_closed_patterns():
+    """The straight-line 32- and 64-leaf cases of the generic node must be
+    closed patterns too (a non-closed one could never occur in these codes)."""
+    src = open(SRC).read()
+    body = src[src.index("__device__ __forceinline__ void blk_node("):]
+    body = body[: body.index("} else if constexpr (PRUNE && M == SPEC_M)")]
+    p64 = [int(x, 16) for x in re.findall(r"case (0x[0-9a-f]+)ull:", body)]
+    p32 = [int(x, 16) for x in re.findall(r"case (0x[0-9a-f]+)u:", body)]
+    assert len(p64) >= 3 and len(p32) >= 3
+    assert all(_is_closed(p, 6) for p in p64)
+    assert all(_is_closed(p, 5) for p in p32)
+
+
+def test_hot_patterns_cover_most_mixed_blocks():
+    """The specialized 64-leaf cases cover most mixed blocks of the benchmark's
+    code (N = 2^20, BSC 0.03, rate 0.75): a performance property, checked so
+    that a change of the construction that shifts the patterns is noticed.
+    Codes of other rates have other frequent patterns and take the generic
+    node more often (still exact)."""
+    log2n, z0, n_frozen = 20, synth.bsc_z0(0.03), 262144
+    src = open(SRC).read()
+    body = src[src.index("__device__ __forceinline__ void blk_node("):]
+    body = body[: body.index("} else if constexpr (PRUNE && M == SPEC_M)")]
+    p64 = {int(x, 16) for x in re.findall(r"case (0x[0-9a-f]+)ull:", body)}
+    mask, _, _ = oracle.frozen_set(log2n, z0, n_frozen)
+    rows = mask.reshape(-1, 64).astype(np.uint64)
+    pats = (rows << np.arange(64, dtype=np.uint64)).sum(axis=1)
+    full = np.uint64(0xFFFFFFFFFFFFFFFF)
+    mixed = [int(p) for p in pats if p not in (0, full, full >> np.uint64(1))]
+    assert sum(p in p64 for p in mixed) / len(mixed) > 0.5
