@@ -536,6 +536,7 @@ __device__ __forceinline__ void blk_node(float a, int O, Blk& B) {
             case 0x000101170117177full: bn = sl_node<64, 0x000101170117177full, FK, DUMP>(a, 0, B); break;
             case 0x0000000100010117ull: bn = sl_node<64, 0x0000000100010117ull, FK, DUMP>(a, 0, B); break;
             case 0x0000000000000001ull: bn = sl_node<64, 0x0000000000000001ull, FK, DUMP>(a, 0, B); break;
+            case 0x7fffffffffffffffull: bn = sl_node<64, 0x7fffffffffffffffull, FK, DUMP>(a, 0, B); break;
             default: known = false; bn = 0; break;
         }
         if (known) B.beta = bn;
@@ -550,6 +551,7 @@ __device__ __forceinline__ void blk_node(float a, int O, Blk& B) {
             case 0x00000001u: bn = sl_node<32, 0x00000001u, FK, DUMP>(a, O, B); break;
             case 0x7fffffffu: bn = sl_node<32, 0x7fffffffu, FK, DUMP>(a, O, B); break;
             case 0xffffffffu: bn = sl_node<32, 0xffffffffu, FK, DUMP>(a, O, B); break;
+            case 0x00000000u: bn = sl_node<32, 0x00000000u, FK, DUMP>(a, O, B); break;
             default: known = false; bn = 0; break;
         }
         if (known) B.beta = sel_lanes(ones64(32) << O, bn, B.beta);
