@@ -354,19 +354,22 @@ constexpr uint32_t ones32() { return M >= 32 ? ~0u : (1u << M) - 1u; }
 //   right: Z_R = Z_lo & Z_hi,  S_R = Z_hi ? (S_lo ^ beta_L) : S_hi
 //   beta = [beta_L ^ beta_R, beta_R];  no zeros: beta = S
 // (hard decisions alone are not SC once an LLR is exactly zero).
-template <int M>
+template <int M, bool CHECK = true>
 __device__ __forceinline__ uint32_t r1_bits(uint32_t S, uint32_t Z) {
     if constexpr (M == 1) {
         return S & ~Z & 1u;
     } else {
-        if (Z == 0) return S;
+        if (CHECK && Z == 0) return S;
+        // children of 4 leaves or fewer take no zero test: straight-line
+        // scalar code is cheaper there than the branches
+        constexpr bool SUB = M > 4;
         constexpr int H = M / 2;
         constexpr uint32_t LO = ones32<H>();
-        const uint32_t bl = r1_bits<H>((S ^ (S >> H)) & LO, (Z | (Z >> H)) & LO);
+        const uint32_t bl = r1_bits<H, SUB>((S ^ (S >> H)) & LO, (Z | (Z >> H)) & LO);
         const uint32_t zhi = Z >> H, shi = S >> H;
         const uint32_t zr = Z & zhi & LO;
         const uint32_t sr = ((zhi & (S ^ bl)) | (~zhi & shi)) & LO;
-        const uint32_t br = r1_bits<H>(sr, zr);
+        const uint32_t br = r1_bits<H, SUB>(sr, zr);
         return (bl ^ br) | (br << H);
     }
 }
@@ -400,7 +403,9 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
             B.has_leaf = true;
         }
         return (a < 0.0f) ? SIGN : 0u;
-    } else if constexpr (P == 0 && FK == 0) {
+    } else if constexpr (P == 0 && FK == 0 && M > 2) {
+        // (a 2-leaf rate-1 node is cheaper as plain f, g and two decisions
+        // in vector registers than as two ballots and a scalar round trip)
         static_assert(M <= 32, "three-state words are 32 bits");
         const uint32_t S = (uint32_t)((ballot(a < 0.0f) >> O) & ALL);
         const uint32_t Z = (uint32_t)((ballot(a == 0.0f) >> O) & ALL);
