@@ -728,6 +728,7 @@ struct SubIO {
     uint32_t* uhat;            // u-hat words of the subtree (out)
     float* leaf;               // leaf LLRs of the subtree (out) or null
     uint64_t* beta_out;        // lane-packed partial sums (out) or null
+    uint64_t* beta_lds;        // second copy of the partial sums (LDS) or null
 };
 
 // State of one subtree decode shared by its node visits.
@@ -827,6 +828,7 @@ __device__ __forceinline__ void subtree_decode(const SubIO io, int lg, float* ld
     const uint64_t acc = x.acc;
 
     if (io.beta_out) io.beta_out[l] = acc;
+    if (io.beta_lds) io.beta_lds[l] = acc;
 
     // u-hat = x-hat G over the subtree: G over k inside the lane word, then
     // across lanes; transpose so lane k holds leaves [64k, 64k + 64).
@@ -1023,7 +1025,7 @@ __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memr
 
 template <int C, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot, float* lds, float* tier,
-                                             uint64_t& sub_ticks) {
+                                             uint32_t* words, uint64_t* lbeta, uint64_t& sub_ticks) {
     const int W = (int)(blockDim.x >> 6);  // wavefronts in the workgroup
     constexpr int R = SubCfg<C>::R;
     const int tid = threadIdx.x;
@@ -1042,7 +1044,7 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
         }
         if (wave == 0) {
             const uint64_t t0 = now_ticks();
-            SubIO io{fd.mask, fd.vals, fd.uhat, fd.leaf, nullptr};
+            SubIO io{fd.mask, fd.vals, fd.uhat, fd.leaf, nullptr, nullptr};
             subtree_decode<C, FK, PRUNE, DUMP>(io, n, lds, fd.llr);
             sub_ticks += now_ticks() - t0;
         }
@@ -1061,6 +1063,15 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
         return reinterpret_cast<float*>(slot + slot_level_offset(n, d));
     };
     const int64_t nsub = (int64_t)1 << D;
+    // mask and value words of subtree s: LDS buffer s & 1, filled by wave 1
+    // while wave 0 decodes the subtree before it
+    constexpr int NW = 1 << (C - 5);
+    const auto stage = [&](int64_t s2) {
+        uint32_t* dst = words + (s2 & 1) * 2 * NW;
+        const int64_t wb = (s2 << C) >> 5;
+        for (int i = tid & 63; i < 2 * NW; i += 64) dst[i] = i < NW ? fd.mask[wb + i] : fd.vals[wb + i - NW];
+    };
+    if (wave == 1) stage(0);
     for (int64_t s = 0; s < nsub; ++s) {
         int t;
         if (s == 0) {
@@ -1069,6 +1080,7 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
             t = __builtin_ctzll((unsigned long long)s);
             for (int q = 1; q <= t; ++q) {
                 combine_words(beta + (s - (1ll << q)) * 64, (1ll << (q - 1)) * 64, tid, W * 64);
+                if (q == 1 && tid < 64) lbeta[tid] ^= lbeta[64 + tid];  // the LDS copy too
                 __syncthreads();
             }
             // g: parent at depth D - t - 1, right child at depth D - t; when
@@ -1076,10 +1088,14 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
             const int dp = D - t - 1;
             const int64_t half = N >> (dp + 1);
             const uint64_t* bl = beta + (s - (1ll << t)) * 64;
+            // (for the two deepest g levels the left sibling's partial sums
+            // are the last one or two subtrees', read from their LDS copy)
             if (t == 0) {
-                sweep_g<C>(level(dp), half, bl, lds, wave, W);
+                sweep_g<C>(level(dp), half, lbeta, lds, wave, W);
+            } else if (t == 1) {
+                sweep2<C, FK, true>(level(dp), half, lbeta, level(D - t), lds, wave, W);
             } else {
-                sweep2<C, FK, true>(level(dp), half, bl, level(D - t), t == 1 ? lds : level(D - t + 1), wave, W);
+                sweep2<C, FK, true>(level(dp), half, bl, level(D - t), level(D - t + 1), wave, W);
             }
             __syncthreads();
         }
@@ -1097,10 +1113,12 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
         if (wave == 0) {
             const uint64_t t0 = now_ticks();
             const int64_t base = s << C;
-            SubIO io{fd.mask + (base >> 5), fd.vals + (base >> 5), fd.uhat + (base >> 5),
-                     DUMP ? fd.leaf + base : nullptr, beta + s * 64};
+            SubIO io{words + (s & 1) * 2 * NW, words + (s & 1) * 2 * NW + NW, fd.uhat + (base >> 5),
+                     DUMP ? fd.leaf + base : nullptr, beta + s * 64, lbeta + (s & 1) * 64};
             subtree_decode<C, FK, PRUNE, DUMP>(io, C, lds, nullptr);
             sub_ticks += now_ticks() - t0;
+        } else if (wave == 1 && s + 1 < nsub) {
+            stage(s + 1);
         }
         __syncthreads();
     }
@@ -1118,6 +1136,8 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __rest
     __shared__ float lds[SubCfg<C>::lds_floats > (1 << C) ? SubCfg<C>::lds_floats : (1 << C)];
     __shared__ float tier[TIER_FLOATS<C>];  // LLR levels of sizes 2^(C+1) and 2^(C+2)
     __shared__ int s_frame;
+    __shared__ uint32_t s_words[2][2 << (C - 5)];  // staged mask and value words of the next subtree
+    __shared__ uint64_t s_beta[2][64];  // partial sums of the last two subtrees (slot s & 1)
     uint8_t* slot = slots + (int64_t)blockIdx.x * slot_bytes;
     while (true) {
         if (threadIdx.x == 0) s_frame = (int)atomicAdd(counter, 1u);
@@ -1128,7 +1148,7 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __rest
         const FrameDesc fd = descs[f];
         uint64_t sub_ticks = 0;
         const uint64_t t0 = prof ? now_ticks() : 0;
-        decode_frame<C, FK, PRUNE, DUMP>(fd, slot, lds, tier, sub_ticks);
+        decode_frame<C, FK, PRUNE, DUMP>(fd, slot, lds, tier, &s_words[0][0], &s_beta[0][0], sub_ticks);
         __syncthreads();
         if (prof && threadIdx.x == 0) {
             atomicAdd(prof + 0, (unsigned long long)sub_ticks);
