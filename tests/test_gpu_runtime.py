@@ -260,6 +260,41 @@ def test_serving_admission_small_arena_cancel_and_nomem():
     ctx.close()
 
 
+def test_serving_queue_full_and_cancel_of_running_request():
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    ctx = lp.Ctx(0)
+    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    small = frame_items(bsc_frames(8, 0.03, 64, [7700]))[0]
+    _say("case: serving queue filled to capacity (no poll, nothing runs)")
+    srv = lp.Server(ctx, arena, poll_us=0)
+    cap = 65536
+    for k in range(cap):
+        srv.submit(small, k)
+    with pytest.raises(lp.PolarError) as err:
+        srv.submit(small, cap)
+    assert err.value.code == lp.POLAR_E_BUSY
+    assert srv.pending() == (cap, 0, 0)
+    srv.close()  # queued requests are dropped, none was started
+
+    _say("case: cancel of a running request")
+    frames = bsc_frames(20, 0.03, 262144, [7701])
+    ref = oracle_many(frames)[0]
+    item = frame_items(frames)[0]
+    srv = lp.Server(ctx, arena, poll_us=0)
+    srv.submit(item, 1)
+    assert srv.poll() == []  # starts the batch; it stays running until a poll reaps it
+    assert srv.pending()[1] == 1
+    assert srv.cancel(1) == lp.POLAR_E_BUSY
+    done = {}
+    _drain(srv, done)
+    srv.close()
+    assert done[1][0] == lp.POLAR_OK
+    assert np.array_equal(bits_host(item["u_hat"], 1 << 20), ref)
+    ctx.close()
+
+
 def test_blocking_serve_with_callbacks():
     import torch
     from paper_1204_5882_amd import polar as lp
