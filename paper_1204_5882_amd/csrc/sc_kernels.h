@@ -298,6 +298,14 @@ struct Blk {
     bool has_leaf;    // lane i: leaf i was reached (not inside a pruned node)
 };
 
+// Decision of a leaf as a sign word: SIGN iff a < 0, so that -0 decides 0.
+// Integer form: a & (a - 1) has its sign bit set exactly for negative nonzero
+// a; no compare, so no scalar mask and no wait before the select.
+__device__ __forceinline__ uint32_t dec_sign(float a) {
+    const uint32_t b = __float_as_uint(a);
+    return b & (b - 1u) & SIGN;
+}
+
 __device__ __forceinline__ uint32_t sel_lanes(uint64_t lanes, uint32_t x, uint32_t y) {
     return lane_bit(lanes) ? x : y;
 }
@@ -402,7 +410,7 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
             B.leaf = a;
             B.has_leaf = true;
         }
-        return (a < 0.0f) ? SIGN : 0u;
+        return dec_sign(a);
     } else if constexpr (P == 0 && FK == 0 && M > 2) {
         // (a 2-leaf rate-1 node is cheaper as plain f, g and two decisions
         // in vector registers than as two ballots and a scalar round trip)
@@ -577,14 +585,13 @@ __device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
         }
         // frozen: the revealed value; information bit: [alpha < 0].  Lane O
         // reads its own frozen bit, so the choice is a lane select.
-        const uint32_t d = lane_bit(B.F) ? B.fv : ((a < 0.0f) ? SIGN : 0u);
+        const uint32_t d = lane_bit(B.F) ? B.fv : dec_sign(a);
         B.beta = sel_lanes(1ull << O, d, B.beta);
     } else {
         constexpr int LG = ilog2<M>();
         int type = 0;
-        uint64_t neg = 0, low = 0;
+        uint64_t low = 0;
         if constexpr (PRUNE) {
-            neg = ballot(a < 0.0f);
             low = ballot(below_rate1_floor<FK, LG>(a));
             // node type from its frozen pattern: 1 rate 0, 2 rate 1, 3 repetition
             const uint64_t fm = (B.F >> O) & ones64(M);
@@ -611,7 +618,7 @@ __device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
         } else if (type == 3) {
             rep_node<M, DUMP>(a, O, B);
         } else {
-            B.beta = sel_lanes(ones64(M) << O, lane_bit(neg) ? SIGN : 0u, B.beta);
+            B.beta = sel_lanes(ones64(M) << O, dec_sign(a), B.beta);
         }
     }
 }
