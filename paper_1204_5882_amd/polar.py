@@ -36,12 +36,6 @@ POLAR_OPT_MAX_SLOTS = 4
 POLAR_OPT_TIMING = 5
 POLAR_OPT_GRAPH = 6
 
-POLAR_E_INVAL = -1
-POLAR_E_NOMEM = -2
-POLAR_E_DEVICE = -3
-POLAR_E_BUSY = -4
-POLAR_E_CANCELLED = -5
-
 # every symbol declared in include/polar.h
 EXPORTED = [
     "polar_last_error", "polar_version", "polar_build_frozen_set", "polar_encode",
