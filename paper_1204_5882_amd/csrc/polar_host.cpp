@@ -362,7 +362,9 @@ int run_graph(polar_ctx* c, const Plan& p, void* ws, hipStream_t s) {
     const uint64_t h = fnv1a(key);
     auto it = c->graphs.find(h);
     if (it != c->graphs.end() && it->second.key != key) {
-        // hash collision: drop the old entry
+        // hash collision: drop the old entry, which may still be running
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "graph cache collision");
         (void)hipGraphExecDestroy(it->second.exec);
         (void)hipHostFree(it->second.pinned);
         c->graphs.erase(it);
