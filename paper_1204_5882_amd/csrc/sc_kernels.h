@@ -799,6 +799,20 @@ __device__ __forceinline__ void sub_node(Lv<C>& v, SubCtx& x, const SubIO& io, i
     }
 }
 
+// u-hat = x-hat G over a subtree of nb blocks, from its lane-packed partial
+// sums: G over k inside the lane word, then across lanes; transposed so that
+// lane k holds leaves [64k, 64k + 64).
+__device__ __forceinline__ void emit_uhat(uint64_t acc, int nb, uint32_t* uhat) {
+    const int l = lane_id();
+    uint64_t u = word_transform(acc, nb);
+    u = lane_transform(u);
+    u = transpose64(u);
+    if (l < nb) {
+        uhat[2 * l] = (uint32_t)u;
+        uhat[2 * l + 1] = (uint32_t)(u >> 32);
+    }
+}
+
 // Decode a subtree of 2^lg leaves, 6 <= lg <= C, on one wavefront.  Input
 // LLRs: at lds + SubCfg<C>::off(lg) when lg > R, else at gsrc (global).
 template <int C, int FK, bool PRUNE, bool DUMP>
@@ -836,16 +850,7 @@ __device__ __forceinline__ void subtree_decode(const SubIO io, int lg, float* ld
 
     if (io.beta_out) io.beta_out[l] = acc;
     if (io.beta_lds) io.beta_lds[l] = acc;
-
-    // u-hat = x-hat G over the subtree: G over k inside the lane word, then
-    // across lanes; transpose so lane k holds leaves [64k, 64k + 64).
-    uint64_t u = word_transform(acc, nb);
-    u = lane_transform(u);
-    u = transpose64(u);
-    if (l < nb) {
-        io.uhat[2 * l] = (uint32_t)u;
-        io.uhat[2 * l + 1] = (uint32_t)(u >> 32);
-    }
+    if (io.uhat) emit_uhat(acc, nb, io.uhat);
 }
 
 // Frames with N < 64: a single block decoder with the node at offset 0.
@@ -1120,15 +1125,20 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
         if (wave == 0) {
             const uint64_t t0 = now_ticks();
             const int64_t base = s << C;
-            SubIO io{words + (s & 1) * 2 * NW, words + (s & 1) * 2 * NW + NW, fd.uhat + (base >> 5),
+            SubIO io{words + (s & 1) * 2 * NW, words + (s & 1) * 2 * NW + NW, nullptr,
                      DUMP ? fd.leaf + base : nullptr, beta + s * 64, lbeta + (s & 1) * 64};
             subtree_decode<C, FK, PRUNE, DUMP>(io, C, lds, nullptr);
             sub_ticks += now_ticks() - t0;
         } else if (wave == 1 && s + 1 < nsub) {
             stage(s + 1);
+        } else if (wave == 2 && s > 0) {
+            // u-hat of the previous subtree, from its partial sums' LDS copy
+            // (slot (s - 1) & 1 is not written again before the next barrier)
+            emit_uhat(lbeta[((s - 1) & 1) * 64 + lane_id()], 1 << (C - 6), fd.uhat + (((s - 1) << C) >> 5));
         }
         __syncthreads();
     }
+    if (wave == 2) emit_uhat(lbeta[((nsub - 1) & 1) * 64 + lane_id()], 1 << (C - 6), fd.uhat + (((nsub - 1) << C) >> 5));
 }
 
 template <int C>
