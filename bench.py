@@ -15,12 +15,26 @@ frozen values are u on the frozen set.  The CPU leg rebuilds its sample of
 frames from the same seeds with the oracle's own frozen set and encoder, and
 checks that they equal the GPU inputs before timing the oracle on them.
 
+Baselines beside the batched figure: the plain decoder (one launch per
+frame, one workgroup, no pruning), the per-frame whole-GPU decoder (the
+production decoder given one frame per call), and the CPU oracle on a
+bounded sample (with its single-thread rate, the CPU model and nproc).
+
 The serving leg (on by default, --no-serve to skip) streams requests of
 N = 2^16 / 2^20 / 2^22 (probabilities 0.5 / 0.35 / 0.15; half BSC p = 0.03
 at rate 0.75, half BIAWGN sigma = 0.97 at rate 0.45, six frozen sets,
-min-sum) through polar_serve_*: first all at once to find the saturation
-throughput, then with Poisson arrivals at a fraction of it, reporting p50 /
-p99 latency from submit to completion.
+min-sum) through polar_serve_* with a 200 GB admission arena: first all at
+once to find the saturation throughput, then with Poisson arrivals at 0.1x
+to 1.3x of it, reporting p50 / p99 latency from submit to each request's
+own completion, overall and per N.
+
+The mixed 512-frame workload is autotuned first (--tune) and the tuned launch
+is reported.
+
+The FER leg (--no-fer to skip) finds, for BSC p = 0.02 at N = 2^16, 2^20 and
+2^24 (the operating points of the paper's Table 1), the largest code rate
+whose SC frame error rate stays at or below 0.1, with the device FER harness,
+and reports the efficiency beta = R / C beside the paper's figures.
 """
 from __future__ import annotations
 
@@ -182,6 +196,18 @@ def host_threads() -> int:
     return max(1, min(n, 16))
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
 def oracle_frames(cfg_name, count):
     """The first count frames of a workload rebuilt from their seeds with the
     oracle's frozen set and encoder (no GPU code involved)."""
@@ -232,7 +258,9 @@ def cpu_baseline(cfg_name, host, boxplus, budget_s=20.0):
     bits = sum(h[0].size for h in sample)
     return dict(value=round(bits / wall / 1e6, 2), unit="Mbit/s", cores=threads, kind="oracle",
                 sample=f"first {count} of {len(host)} frames, {threads} host threads, {wall:.2f} s wall, "
-                       f"{one * count:.1f} s of single-thread work"), outs, same_inputs
+                       f"{one * count:.1f} s of single-thread work",
+                single_thread_Mbit_s=round(sample[0][0].size / one / 1e6, 2),
+                cpu_model=cpu_model(), nproc=os.cpu_count()), outs, same_inputs, sample
 
 
 # ---------------------------------------------------------------- serving leg
@@ -241,9 +269,15 @@ SERVE_MIX = [  # (log2n, probability)
 SERVE_CODES = [("bsc", 0.03, 0.75), ("biawgn", 0.97, 0.45)]
 
 
-def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, load=0.8, seed=50000):
+SERVE_LOADS = (0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 1.0, 1.1, 1.3)
+
+
+def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, loads=SERVE_LOADS, seed=50000,
+              arena_gb=200.0):
     """Requests drawn from a pool of resident frames (pool_per_size distinct
-    frames per (N, code)); each request writes its own u-hat buffer."""
+    frames per (N, code)); each request writes its own u-hat buffer.  First
+    all requests are queued at once (saturation throughput), then Poisson
+    arrivals are offered at each fraction of it in loads."""
     g = np.random.default_rng(seed)
     pool = {}
     for log2n, _ in SERVE_MIX:
@@ -273,9 +307,11 @@ def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, load=0.8, seed=5
         it = dict(src)
         it["u_hat"] = torch.zeros(lp.n_words(log2n), dtype=torch.int32, device=dev)
         reqs.append(it)
+    logs = np.array([it["log2n"] for it in reqs])
     bits = np.array([1 << it["log2n"] for it in reqs], np.float64)
     ctx = lp.Ctx(0)
-    arena_bytes = 8 << 30
+    free = torch.cuda.mem_get_info(dev)[0]
+    arena_bytes = min(int(arena_gb * 1e9), int(free * 0.8)) & ~255
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
@@ -284,6 +320,7 @@ def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, load=0.8, seed=5
         lat = np.zeros(len(reqs))
         done = 0
         nxt = 0
+        max_batches = 0
         t0 = time.perf_counter()
         while done < len(reqs):
             now = time.perf_counter() - t0
@@ -295,26 +332,108 @@ def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, load=0.8, seed=5
                     raise RuntimeError(f"request {rid} failed with {st}")
                 lat[rid] = l
                 done += 1
+            max_batches = max(max_batches, srv.stats()[0])
         wall = time.perf_counter() - t0
         srv.close()
-        return wall, lat
+        return wall, lat, max_batches
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)) * 1e3, 3)
 
     # saturation: everything queued at t = 0
     run(np.zeros(len(reqs)))  # warm-up
-    wall_sat, _ = run(np.zeros(len(reqs)))
+    wall_sat, lat_sat, mb_sat = run(np.zeros(len(reqs)))
     sat_mbit = bits.sum() / wall_sat / 1e6
-    rate = load * sat_mbit * 1e6 / bits.mean()  # requests per second
-    arrivals = np.cumsum(g.exponential(1.0 / rate, len(reqs)))
-    wall, lat = run(arrivals)
-    ctx.close()
+    sweep = []
+    for load in loads:
+        rate = load * sat_mbit * 1e6 / bits.mean()  # requests per second
+        arrivals = np.cumsum(g.exponential(1.0 / rate, len(reqs)))
+        wall, lat, mb = run(arrivals)
+        row = dict(load=load, arrival_rate_req_s=round(rate, 1), Mbit_s=round(bits.sum() / wall / 1e6, 1),
+                   p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), max_batches_resident=mb)
+        row["by_log2n"] = {str(l): dict(p50_ms=pct(lat[logs == l], 50), p99_ms=pct(lat[logs == l], 99))
+                           for l in sizes if (logs == l).any()}
+        sweep.append(row)
+    head = next(r for r in sweep if r["load"] == 0.8)
     return dict(requests=len(reqs), mix="N=2^16/2^20/2^22 at 0.5/0.35/0.15; BSC p=0.03 R=0.75 and BIAWGN "
                 "sigma=0.97 R=0.45 (min-sum), Poisson arrivals",
-                saturation_Mbit_s=round(sat_mbit, 1), load=load, arrival_rate_req_s=round(rate, 1),
-                Mbit_s=round(bits.sum() / wall / 1e6, 1),
-                p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
-                p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3),
-                mean_ms=round(float(lat.mean()) * 1e3, 3), arena_bytes=arena_bytes,
-                note="latency = host time from submit to the poll that sees the request's batch done")
+                saturation_Mbit_s=round(sat_mbit, 1), saturation_p50_ms=pct(lat_sat, 50),
+                saturation_p99_ms=pct(lat_sat, 99), load=0.8, Mbit_s=head["Mbit_s"], p50_ms=head["p50_ms"],
+                p99_ms=head["p99_ms"], sweep=sweep, arena_bytes=arena_bytes,
+                note="latency = host time from submit to the poll that sees the request's own frame done; "
+                     "each request is charged its own footprint in the arena")
+
+
+# Table 1 of the paper, BSC rows: (log2 N, efficiency beta, FER, Mbit/s on
+# one core of an Intel Core i5 670 at 3.47 GHz, fixed-point phi-table SC)
+PAPER_TABLE1_BSC2 = {16: (0.935, 0.09, 10.9), 20: (0.963, 0.11, 9.5), 24: (0.980, 0.08, 8.3)}
+
+
+def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1, seed=12345):
+    """Largest code rate (frozen set by Bhattacharyya ranking) whose measured
+    SC frame error rate stays at or below the target, per N, by bisection on
+    the number K of information bits; each point decodes `frames` synthetic
+    BSC frames with the device harness (generation, decoding and error
+    counting on the GPU).  Efficiency beta = K / (N C)."""
+    import math
+
+    cap = 1.0 + p * math.log2(p) + (1.0 - p) * math.log2(1.0 - p)
+    frames = frames or {16: 1024, 20: 256, 24: 128}
+    ctx = lp.Ctx(0)
+    out = []
+    for log2n in sizes:
+        n = 1 << log2n
+        nfr = frames[log2n]
+
+        def fer_at(k, nfr=nfr, log2n=log2n, n=n):
+            words, _, _ = lp.build_frozen_set(log2n, synth.bsc_z0(p), n - k, 0.1)
+            mdev = torch.from_numpy(words.view(np.int32).copy()).to(dev)
+            res, _ = ctx.fer_bsc(log2n, p, mdev, nfr, seed=seed)
+            return res["frame_errors"] / nfr
+
+        lo, hi = int(0.5 * cap * n), int(cap * n)
+        steps = 0
+        while hi - lo > max(1, n >> 10):
+            mid = (lo + hi) // 2
+            if fer_at(mid) <= target:
+                lo = mid
+            else:
+                hi = mid
+            steps += 1
+        # the operating point, timed
+        words, _, _ = lp.build_frozen_set(log2n, synth.bsc_z0(p), n - lo, 0.1)
+        mdev = torch.from_numpy(words.view(np.int32).copy()).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, _ = ctx.fer_bsc(log2n, p, mdev, nfr, seed=seed + 1)
+        wall = time.perf_counter() - t0
+        paper = PAPER_TABLE1_BSC2.get(log2n)
+        out.append(dict(log2n=log2n, K=lo, rate=round(lo / n, 5), beta=round(lo / n / cap, 4),
+                        fer=round(res["frame_errors"] / nfr, 4), frames=nfr, bisection_steps=steps,
+                        harness_Mbit_s=round(nfr * n / wall / 1e6, 1),
+                        paper=None if paper is None else dict(beta=paper[0], fer=paper[1], Mbit_s=paper[2])))
+    ctx.close()
+    return dict(channel=f"BSC p={p}", capacity=round(cap, 6), target_fer=target, rule="largest K with FER <= target "
+                "(Bhattacharyya-ranked frozen set, FP32 min-sum SC, fresh frames for the reported point)",
+                points=out, note="the paper's frozen sets come from density evolution, not Bhattacharyya ranking")
+
+
+def copy_bandwidth(torch, dev, mib=1024):
+    """Device-to-device copy of mib MiB timed with events: bytes read + written / time."""
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / 5
+    del src, dst
+    return round(2 * (mib << 20) / (ms / 1e3) / 1e9, 1)
 
 
 def main(argv=None):
@@ -332,6 +451,13 @@ def main(argv=None):
     ap.add_argument("--graph", type=int, default=0, help="replay the batch through a HIP graph")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-arena-gb", type=float, default=200.0,
+                    help="serving arena (device memory admission budget), GB")
+    ap.add_argument("--tune", type=int, default=-1,
+                    help="autotune the launch on the workload first (default: on for the mixed workload)")
+    ap.add_argument("--no-fer", action="store_true", help="skip the FER / efficiency leg")
+    ap.add_argument("--per-frame-frames", type=int, default=8,
+                    help="frames timed with the per-frame whole-GPU decoder (one batched call per frame)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling the HBM byte counters of a profile) before the benchmark")
@@ -372,6 +498,11 @@ def main(argv=None):
     if args.graph:
         ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
     frames = lp.make_frames(items)
+    tune = args.tune if args.tune >= 0 else int(args.config.startswith("mixed"))
+    tuned = None
+    if tune:
+        print("[bench] autotuning the launch on this workload", file=sys.stderr, flush=True)
+        tuned = ctx.autotune(items, reps=3)
     ctx.ensure_workspace(frames, n)
     torch.cuda.synchronize()
     print(f"[bench] {n} frames, {total_bits / 1e6:.1f} Mbit; warmup {args.warmup}, steps {args.steps}",
@@ -399,11 +530,18 @@ def main(argv=None):
                            bits_per_step=total_bits, info_bits_per_step=info_bits,
                            f_kind="boxplus" if cfg["fkind"] else "minsum", prune=bool(args.prune),
                            graph=bool(args.graph), decoder_source=source,
-                           launch=ctx.query_launch(cfg["fkind"], max(it["log2n"] for it in items), n)),
+                           launch=ctx.query_launch(cfg["fkind"], max(it["log2n"] for it in items), n),
+                           tuned=tuned),
                roofline=roof,
                kernel_ms_mean=round(ev_ms, 3), kernel_ms_min=round(float(np.min(per)), 3),
                info_Mbit_s=round(info_bits / (ms_step / 1e3) / 1e6, 1),
                alg_bytes_per_step=int(alg_bytes))
+    # compulsory traffic: channel LLRs, frozen mask and values read once, u-hat
+    # written once (4.375 B/bit); its share of the roofline time
+    compulsory = total_bits * 4.375
+    out["compulsory"] = dict(bytes=int(compulsory), B_per_bit=4.375,
+                             frac=round(compulsory / (ev_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4))
+    out["copy_GB_s"] = copy_bandwidth(torch, dev)
 
     # serial leaf region: share of frame time spent in register-resident
     # subtree decoding, from the library's timing counters (separate run)
@@ -430,22 +568,61 @@ def main(argv=None):
         out["plain"] = dict(value=round(pbits / pw / 1e6, 2), unit="Mbit/s", frames=k,
                             note="one launch per frame, one workgroup, no pruning, serial on one stream")
         out["speedup_vs_plain"] = round(value / (pbits / pw / 1e6), 1)
+        # the stronger per-frame baseline: the production decoder (pruning,
+        # every option as above) handed one frame per call, calls serial on
+        # the stream: the whole GPU working on a single frame at a time
+        k = min(args.per_frame_frames, n)
+        one = [lp.make_frames([it]) for it in items[:k]]
+        for fr in one[:2]:
+            ctx.decode_batch(fr, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for fr in one:
+            ctx.decode_batch(fr, 1)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        pbits = sum(1 << it["log2n"] for it in items[:k])
+        out["per_frame"] = dict(value=round(pbits / pw / 1e6, 2), unit="Mbit/s", frames=k,
+                                note="the batched decoder given one frame per call, serial on one stream")
+        out["speedup_vs_per_frame"] = round(value / (pbits / pw / 1e6), 1)
+
+    if not args.no_fer:
+        print("[bench] FER / efficiency leg", file=sys.stderr, flush=True)
+        out["fer"] = fer_leg(lp, torch, dev)
 
     if not args.no_serve:
         print("[bench] serving leg", file=sys.stderr, flush=True)
-        out["serving"] = serve_leg(lp, torch, dev, n_requests=args.serve_requests)
+        out["serving"] = serve_leg(lp, torch, dev, n_requests=args.serve_requests, arena_gb=args.serve_arena_gb)
 
     if not args.no_cpu:
         print("[bench] CPU oracle leg", file=sys.stderr, flush=True)
-        cb, outs, same_inputs = cpu_baseline(args.config, host, boxplus=bool(cfg["fkind"]))
+        cb, outs, same_inputs, sample = cpu_baseline(args.config, host, boxplus=bool(cfg["fkind"]))
         out["cpu_baseline"] = cb
         out["oracle_inputs_equal_gpu_inputs"] = same_inputs
-        # the batched GPU output of the timed run, checked on the same sample
+        # the batched GPU output of the timed run, checked on the same sample:
+        # min-sum bit for bit; box-plus against the FP64 oracle re-run with the
+        # GPU's decisions as partial sums (teacher forcing), frozen positions
+        # equal to the frozen values, and information bits differing only
+        # where the oracle's leaf LLR has |L| < 1e-6
         ok = True
+        tolerated = 0
         for k, ref in enumerate(outs):
             got = synth.unpack_bits(items[k]["u_hat"].cpu().numpy().view(np.uint32), items[k]["llr"].numel())
-            ok &= bool(np.array_equal(got, ref)) if not cfg["fkind"] else True
+            if not cfg["fkind"]:
+                ok &= bool(np.array_equal(got, ref))
+            else:
+                import oracle
+
+                llr, mask, fval = sample[k]
+                u_or, l_ref, _ = oracle.sc_decode(llr, mask, fval, boxplus=True, teacher=got, want_leaf=True)
+                fz = mask == 1
+                dis = (u_or != got) & ~fz
+                ok &= bool(np.array_equal(got[fz], fval[fz])) and bool(np.all(np.abs(l_ref[dis]) < 1e-6))
+                tolerated += int(dis.sum())
         out["oracle_agrees_on_sample"] = ok
+        out["oracle_check"] = dict(frames=len(outs), rule="bit-exact" if not cfg["fkind"] else
+                                   "teacher-forced FP64 oracle, |L_ref| < 1e-6 at differing decisions",
+                                   tolerated_differences=tolerated)
     out["paper_context"] = dict(value=9.5, unit="Mbit/s", note="SC decoding, BSC 2%, N=2^20, one core of an "
                                 "Intel Core i5 670 @3.47 GHz, fixed point (Table 1); different machine and workload")
     print(json.dumps(out), flush=True)

@@ -117,18 +117,27 @@ typedef struct polar_ctx polar_ctx;
 #define POLAR_OPT_PRUNE 1       /* 0/1: exact rate-0 / rate-1 node shortcuts (default 1) */
 #define POLAR_OPT_CUTOVER 2     /* log2 of the subtree decoded by one wavefront from
                                    LDS / registers (larger nodes stream through HBM):
-                                   10, 11 or 12; 0 = automatic (default: the tuned
+                                   8 .. 12; 0 = automatic (default: the tuned
                                    value, else 12).  Leaf-LLR dumps and unpruned
                                    decoding always use 12.                                */
 #define POLAR_OPT_WG_WAVES 3    /* wavefronts per workgroup: 4 or 8; 0 = automatic (8) */
-#define POLAR_OPT_MAX_SLOTS 4   /* max frames in flight (workgroups); 0 = automatic
-                                   (the tuned value, else 2 per compute unit)           */
+#define POLAR_OPT_MAX_SLOTS 4   /* max workgroups of a launch; 0 = automatic (the tuned
+                                   value, else every workgroup that can be resident at
+                                   once: compute units x the variant's occupancy).
+                                   Never more than can be resident.                     */
 #define POLAR_OPT_TIMING 5      /* device pointer (as an integer) to 8 zeroed uint64
                                    counters, or 0 = off.  Decoding then adds, per frame:
                                    [0] ticks spent in register-resident subtree decoding
                                    (the serial leaf region), [1] ticks for the whole
                                    frame, [2] 1.  Ticks are the 100 MHz s_memrealtime
                                    clock, summed over frames in flight.              */
+#define POLAR_OPT_FWG 7         /* frames per workgroup for frames of at most 2^cutover
+                                   leaves, each decoded by its own wavefront: 1 .. waves
+                                   (capped by the LDS the frames' subtree levels need:
+                                   4 at 2^12 with cutover 12); 0 = automatic (the tuned
+                                   value, else enough to spread the small frames over
+                                   every workgroup).  Frames above 2^cutover are decoded
+                                   by a whole workgroup each.                          */
 #define POLAR_OPT_GRAPH 6       /* 0/1: polar_sc_decode_batch replays each distinct batch
                                    (same descriptors, options and workspace) through a
                                    cached HIP graph [descriptor copy, counter reset,
@@ -178,48 +187,70 @@ int polar_sc_decode_batch(polar_ctx* ctx, const polar_frame* frames, int n_frame
 int polar_sc_decode_plain(polar_ctx* ctx, const polar_frame* frames, int n_frames, void* stream);
 
 /*
- * Autotuner.  Times every built launch configuration (cutover 10..12,
- * 4 or 8 wavefronts per workgroup, 1..3 frames in flight per compute unit)
- * on these frames with the context's workspace (configurations that do not
- * fit it are skipped), median of reps runs after one warm-up, and records
- * the fastest for (f_kind, largest log2n of the frames).  Later batches whose
+ * Autotuner.  Times the built launch configurations on these frames with the
+ * context's workspace (configurations that do not fit it are skipped):
+ * cutover 8 .. 12, 4 or 8 wavefronts per workgroup, workgroups per launch
+ * (half the compute units, all of them, every resident slot), frames per
+ * workgroup 1 / 2 / 4 / 8 for frames of at most 2^cutover leaves, and the
+ * unpruned decoder; median of reps runs after one warm-up each.  Records the
+ * fastest for (f_kind, largest log2n of the frames); later batches whose
  * largest frame has that size use it unless an option is set explicitly.
+ * Every configuration gives the same results (the shortcuts are exact).
  * Frames must share one f_kind, must not request leaf LLRs, and pruning must
- * be on.  The frames' u_hat buffers are overwritten.  Outputs may be NULL.
+ * be on in the context.  The frames' u_hat buffers are overwritten.  The
+ * best_* outputs describe the launch a batch of these frames now gets;
+ * n_candidates the number of configurations timed.  Outputs may be NULL.
  */
 int polar_autotune(polar_ctx* ctx, const polar_frame* frames, int n_frames, int reps, void* stream,
-                   int* best_cutover, int* best_waves, int* best_slots, double* best_ms);
+                   int* best_cutover, int* best_waves, int* best_slots, int* best_fwg, int* best_prune,
+                   double* best_ms, int* n_candidates);
 
-/* Launch configuration a batch of n_frames frames of f_kind whose largest
-   frame has log2n would use under the context's options and tuned table. */
+/* Launch configuration a batch of n_frames frames of f_kind, each of 2^log2n
+   leaves, would use under the context's options and tuned table. */
 int polar_query_launch(const polar_ctx* ctx, int f_kind, int log2n, int n_frames, int* cutover, int* waves,
-                       int* slots);
+                       int* slots, int* fwg, int* prune);
 
 /* Tuned table: forget it, or save / load it as JSON
-   {"libpolar_tune": 1, "entries": [{"f_kind", "log2n", "cutover", "waves", "slots"}, ...]}.
-   Loading merges into the table and rejects out-of-range entries. */
+   {"libpolar_tune": 1, "entries": [{"f_kind", "log2n", "cutover", "waves", "slots",
+   "fwg", "prune"}, ...]} ("fwg" and "prune" optional on load).  Loading merges
+   into the table and rejects out-of-range entries. */
 int polar_tune_clear(polar_ctx* ctx);
 int polar_tune_save(const polar_ctx* ctx, const char* path);
 int polar_tune_load(polar_ctx* ctx, const char* path);
 
 /*
- * Serving.  Requests (one frame each, caller-owned device buffers that must
+ * Serving (Section 4: frames are independent, so requests are decoded side by
+ * side).  Requests (one frame each, caller-owned device buffers that must
  * stay valid until the request completes) are queued, admitted against a
  * caller-provided device arena and decoded in batches by the batch decoder on
  * up to four internal streams at once: a new batch starts on an idle stream
  * with the requests that have arrived, in arrival order, as many as fit the
- * free arena (and at most max_slots), while earlier batches still run.  A
- * batch needs the polar_workspace_bytes of its frames; a request too large
- * for the whole arena completes with POLAR_E_NOMEM.  Results equal those of
- * decoding the frame alone.  Latency is host time from submit to the poll
- * that finds the request's batch finished.  A server is used from one host
- * thread.
+ * free arena (and at most max_slots), while earlier batches still run.  Each
+ * request is charged its own footprint in the arena: a 64-byte descriptor
+ * plus, above 2^12 leaves, a scratch slot of about 4N + N/8 bytes for its own
+ * N (256 bytes of counters per batch).  A request too large for the whole
+ * arena completes with POLAR_E_NOMEM.
+ *
+ * Ordering: a batch starts only after all work enqueued on input_stream
+ * before the batch was formed, so request inputs (LLRs, frozen words, and
+ * any fill of u_hat) produced on that stream before submit are complete when
+ * they are read.  Inputs produced on other streams must be synchronised by
+ * the caller before submit.
+ *
+ * Completion is per request: the decoder flags a frame as soon as its u_hat
+ * is written and globally visible, and the next poll reports it, while the
+ * rest of its batch may still run.  Results equal those of decoding the
+ * frame alone.  Latency is host time from submit to the poll that sees the
+ * request's flag.  A server is used from one host thread.
  */
 typedef struct polar_serve_cfg {
     size_t arena_bytes;  /* >= 4096                                             */
     void* arena;         /* device, 256-byte aligned, caller-owned               */
-    int max_slots;       /* max requests per batch; 0 = 2 per compute unit       */
+    int max_slots;       /* max requests per batch; 0 = the workgroups of the
+                            default decoder that can be resident at once        */
     int poll_us;         /* idle sleep of polar_serve between polls (0 = spin)   */
+    void* input_stream;  /* stream the request inputs are produced on (NULL =
+                            the null stream); see Ordering above                */
 } polar_serve_cfg;
 
 typedef struct polar_completion {
@@ -238,6 +269,9 @@ int polar_serve_submit(polar_server* srv, const polar_frame* req, uint64_t req_i
 int polar_serve_poll(polar_server* srv, polar_completion* out, int max_out, int* n_out);
 /* Requests waiting, running, and completed but not yet returned by a poll. */
 int polar_serve_pending(const polar_server* srv, int* queued, int* running, int* completed);
+/* Batches on the device (at most four) and the arena bytes they hold; a
+   batch is counted until the poll that finds its last work finished. */
+int polar_serve_stats(const polar_server* srv, int* batches_running, size_t* arena_used);
 /* Cancel a queued request (it completes with POLAR_E_CANCELLED); POLAR_E_BUSY
    if it is already running, POLAR_E_INVAL if unknown. */
 int polar_serve_cancel(polar_server* srv, uint64_t req_id);
@@ -253,6 +287,58 @@ int polar_serve_close(polar_server* srv);
 typedef int (*polar_next_fn)(void* user, polar_frame* req, uint64_t* req_id); /* 0 ok, 1 none yet, 2 end */
 typedef void (*polar_done_fn)(void* user, uint64_t req_id, int status, double latency_s);
 int polar_serve(polar_ctx* ctx, const polar_serve_cfg* cfg, polar_next_fn next, polar_done_fn done, void* user);
+
+/*
+ * Frame-error-rate harness (Table 1's FER at a code rate; Section 2.1 eq. (5)
+ * puts the FER into the key rate; Section 3 sizes frozen sets for FER 0.1):
+ * synthetic BSC frames generated on the device, decoded by the batch decoder
+ * and checked against the transmitted u, all on the GPU.
+ *
+ * Frames come from the counter-based generator Philox4x32-10 (Salmon et al.,
+ * SC'11), so frame f depends only on (seed, f):
+ *   key = (seed mod 2^32, f)
+ *   u word w             = Philox((w >> 2, 0, 0, 0), key)[w & 3]
+ *                          (N < 32: the low N bits of word 0)
+ *   channel error, bit i = Philox((i >> 2, 1, 0, 0), key)[i & 3] < floor(p 2^32)
+ *   x = u G_N; L_i = +L0 where x_i equals the error bit, else -L0, with
+ *   L0 = ln((1 - p) / p) computed in double and rounded once to float32
+ *   frozen values = u on the frozen set
+ * A frame is in error when its u-hat differs from u in any position.
+ *
+ * polar_fer_generate_bsc writes frames frame0 .. frame0 + n_frames - 1:
+ *   u, frozen_vals, x_scratch  device, n_frames * max(1, N/32) words each
+ *   llr                        device, n_frames * N floats, 16-byte aligned
+ * polar_fer_bsc generates, decodes (under the context's options) and counts
+ * cfg->n_frames frames in steps of cfg->batch, in caller memory: workspace of
+ * polar_fer_workspace_bytes (256-byte aligned), bit_errors (device, one
+ * uint32 per frame: u-hat bits that differ from u).  It synchronises the
+ * stream before filling *out (host).
+ */
+typedef struct polar_fer_cfg {
+    int32_t log2n;                /* 1 .. POLAR_MAX_LOG2N                              */
+    int32_t f_kind;               /* POLAR_F_MINSUM or POLAR_F_BOXPLUS                  */
+    double p;                     /* BSC crossover probability, 0 < p < 1/2            */
+    const uint32_t* frozen_mask;  /* device, max(1, N/32) words, 1 = frozen            */
+    uint64_t seed;                /* low 32 bits used                                  */
+    int64_t frame0;               /* first frame index; frame indices < 2^32           */
+    int64_t n_frames;             /* >= 0                                              */
+    int32_t batch;                /* frames per step; 0 = automatic                    */
+    int32_t reserved;
+} polar_fer_cfg;
+
+typedef struct polar_fer_result {
+    int64_t frames;
+    int64_t frame_errors;
+    int64_t bit_errors;
+} polar_fer_result;
+
+int polar_fer_generate_bsc(int log2n, double p, const uint32_t* frozen_mask, uint64_t seed, int64_t frame0,
+                           int n_frames, uint32_t* u, uint32_t* frozen_vals, uint32_t* x_scratch, float* llr,
+                           void* stream);
+/* Returns 0 on invalid arguments. */
+size_t polar_fer_workspace_bytes(const polar_ctx* ctx, const polar_fer_cfg* cfg);
+int polar_fer_bsc(polar_ctx* ctx, const polar_fer_cfg* cfg, void* workspace, size_t ws_bytes,
+                  uint32_t* bit_errors, polar_fer_result* out, void* stream);
 
 /*
  * Diagnostics: exercises the cross-lane moves (DPP row shifts, permlane

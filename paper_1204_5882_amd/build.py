@@ -38,7 +38,8 @@ COMMON = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["sc_device.hip", "polar_host.cpp", "polar_tune.cpp", "polar_serve.cpp"] + sorted(
+SOURCES = ["sc_device.hip", "polar_host.cpp", "polar_tune.cpp", "polar_serve.cpp",
+           "polar_fer.hip"] + sorted(
     os.path.relpath(f, CSRC) for f in glob.glob(os.path.join(CSRC, "variants", "*.hip")))
 
 # Device code runs with the IEEE mode bit off: min/max then need no NaN

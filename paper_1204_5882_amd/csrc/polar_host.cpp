@@ -166,8 +166,30 @@ constexpr size_t kHeaderBytes = 256;  // work counters
 constexpr size_t kMaxGraphs = 16;
 }  // namespace
 
-int Stager::upload(const FrameDesc* d, size_t n, void* dst, hipStream_t s) {
+int Stager::reserve(size_t n) {
+    if (!ev) {
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    if (n <= cap) return ok();
+    if (pending) {
+        hipError_t e = hipEventSynchronize(ev);
+        if (e != hipSuccess) return hip_fail(e, "descriptor staging");
+        pending = false;
+    }
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc((void**)&buf, n * sizeof(FrameDesc), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "pinned descriptor buffer");
+    cap = n;
+    return ok();
+}
+
+int Stager::upload(const FrameDesc* d, size_t n, void* dst, hipStream_t s, bool may_grow) {
     if (n == 0) return ok();
+    if (!may_grow && (n > cap || !ev))
+        return fail(POLAR_E_INVAL, "%zu descriptors exceed the %zu reserved for this call", n, cap);
     if (!ev) {
         hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -226,38 +248,116 @@ int validate_frames(const polar_frame* frames, int n_frames) {
     return ok();
 }
 
-LaunchCfg group_cfg(const polar_ctx* c, int fk, int maxlog, int count, bool dump, bool plain) {
+int occupancy(const polar_ctx* c, int cutover, int fk, bool dump, int waves, bool prune, int small_log2n) {
+    // cache slot: cutover 8..12, f_kind, dump, prune, small_log2n -1..24, waves 1..8
+    const int key = (((((cutover - 8) * 2 + fk) * 2 + (dump ? 1 : 0)) * 2 + (prune ? 1 : 0)) * 26 + small_log2n + 1) *
+                        8 + (waves - 1);
+    const bool cacheable = cutover >= 8 && cutover <= 12 && waves >= 1 && waves <= 8 && small_log2n >= -1 &&
+                           small_log2n <= POLAR_MAX_LOG2N && key >= 0 && key < (int)c->occ_cache.size();
+    if (cacheable && c->occ_cache[(size_t)key] > 0) return c->occ_cache[(size_t)key];
+    DeviceGuard g(c->device);
+    int occ = g.ok ? polar_dev_occupancy(cutover, fk, prune ? 1 : 0, dump ? 1 : 0, waves, small_log2n) : 0;
+    occ = std::max(1, occ);
+    if (cacheable) c->occ_cache[(size_t)key] = occ;
+    return occ;
+}
+
+LaunchCfg group_cfg(const polar_ctx* c, int fk, bool dump, const SizeHist& h, bool plain, const LaunchCfg* force) {
     LaunchCfg cfg;
     if (plain) {
         cfg.cutover = 12;
         cfg.waves = 4;
         cfg.slots = 1;
+        cfg.fwg = 1;
+        cfg.prune = 0;
         return cfg;
     }
-    cfg.slots = 2 * c->n_cu;
+    cfg.slots = 0;
     cfg.waves = 8;  // the level sweeps are bound by the bytes in flight per workgroup
-    auto it = c->tuned.find({fk, maxlog});
-    if (it != c->tuned.end()) cfg = it->second;
-    if (c->cutover) cfg.cutover = c->cutover;
-    if (c->waves) cfg.waves = c->waves;
-    if (c->max_slots) cfg.slots = c->max_slots;
-    if (dump || !c->prune) cfg.cutover = 12;
-    cfg.slots = std::max(1, std::min(cfg.slots, count));
+    if (force) {
+        cfg = *force;
+    } else {
+        auto it = c->tuned.find({fk, h.maxlog});
+        if (it != c->tuned.end()) cfg = it->second;
+        if (c->cutover) cfg.cutover = c->cutover;
+        if (c->waves) cfg.waves = c->waves;
+        if (c->max_slots) cfg.slots = c->max_slots;
+        if (c->fwg) cfg.fwg = c->fwg;
+    }
+    // pruning switched off in the context wins over a tuned choice
+    if (!c->prune) cfg.prune = 0;
+    else if (cfg.prune < 0) cfg.prune = 1;
+    if (dump || !cfg.prune) cfg.cutover = 12;
+    // at most the workgroups that can be resident at once
+    const int cap = c->n_cu * occupancy(c, cfg.cutover, fk, dump, cfg.waves, cfg.prune != 0);
+    const int asked = cfg.slots;
+    if (cfg.slots <= 0 || cfg.slots > cap) cfg.slots = cap;
+    int n_small = 0, lg_small = 0;
+    for (int l = 0; l <= std::min(cfg.cutover, (int)POLAR_MAX_LOG2N); ++l)
+        if (h.n[l]) {
+            n_small += h.n[l];
+            lg_small = l;
+        }
+    const int n_big = h.count - n_small;
+    cfg.slots = std::max(1, std::min(cfg.slots, n_big));
+    if (!n_small) {
+        cfg.fwg = 1;
+        cfg.small_slots = 1;
+        return cfg;
+    }
+    // small frames: fwg wavefronts (one frame each) per workgroup; the
+    // default holds the most frames in flight (resident workgroups x fwg,
+    // up to the frames there are), the smallest such fwg on ties
+    const int f_max = std::max(1, polar_dev_max_fwg(cfg.cutover, lg_small, cfg.waves));
+    auto small_cap = [&](int fw) {
+        int sc = c->n_cu * occupancy(c, cfg.cutover, fk, dump, fw, cfg.prune != 0, lg_small);
+        return std::max(1, asked > 0 ? std::min(sc, asked) : sc);
+    };
+    if (cfg.fwg <= 0) {
+        cfg.fwg = 1;
+        int64_t best = 0;
+        for (int fw = 1; fw <= f_max; ++fw) {
+            const int64_t inflight = std::min<int64_t>((int64_t)small_cap(fw) * fw, n_small);
+            if (inflight > best) {
+                best = inflight;
+                cfg.fwg = fw;
+            }
+        }
+    }
+    cfg.fwg = std::max(1, std::min(cfg.fwg, f_max));
+    cfg.small_slots = std::max(1, std::min(small_cap(cfg.fwg), (n_small + cfg.fwg - 1) / cfg.fwg));
     return cfg;
 }
 
+int64_t group_slot_bytes(const SizeHist& h, const LaunchCfg& cfg, bool per_frame, int64_t* per_wg) {
+    int64_t sum = 0, big = 0;
+    for (int l = cfg.cutover + 1; l <= POLAR_MAX_LOG2N; ++l)
+        if (h.n[l]) {
+            const int64_t b = polar_dev_slot_bytes(l, cfg.cutover);
+            sum += b * h.n[l];
+            big = std::max(big, b);
+        }
+    if (per_wg) *per_wg = big;
+    return per_frame ? sum : big * cfg.slots;
+}
+
 void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool plain, Plan& p,
-               const LaunchCfg* force) {
-    std::vector<int> order((size_t)n_frames);
-    std::iota(order.begin(), order.end(), 0);
-    // group by (f_kind, leaf dump); inside a group, most work first
+               const LaunchCfg* force, bool per_frame) {
+    // order: by (f_kind, leaf dump), inside a group most work (largest N)
+    // first, ties in submission order: a stable counting sort over the
+    // 4 x 25 keys (no allocation once the plan's vectors have the capacity)
+    constexpr int NL = POLAR_MAX_LOG2N + 1;
     auto key = [&](int i) { return frames[i].f_kind * 2 + (frames[i].leaf_llr ? 1 : 0); };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (key(a) != key(b)) return key(a) < key(b);
-        return frames[a].log2n > frames[b].log2n;
-    });
+    auto bucket = [&](int i) { return key(i) * NL + (POLAR_MAX_LOG2N - frames[i].log2n); };
+    int start[4 * NL + 1] = {};
+    for (int i = 0; i < n_frames; ++i) ++start[bucket(i) + 1];
+    for (int b = 0; b < 4 * NL; ++b) start[b + 1] += start[b];
+    std::vector<int>& order = p.order;
+    order.resize((size_t)n_frames);
+    for (int i = 0; i < n_frames; ++i) order[(size_t)start[bucket(i)]++] = i;
     p.descs.clear();
     p.groups.clear();
+    p.per_frame = per_frame && !plain;
     for (int k = 0; k < n_frames; ++k) {
         const polar_frame& f = frames[order[(size_t)k]];
         FrameDesc d{};
@@ -268,66 +368,105 @@ void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool
         d.leaf = f.leaf_llr;
         d.log2n = f.log2n;
         d.fkind = f.f_kind;
+        d.slot = nullptr;
+        d.done_idx = 0xffffffffu;
+        d.done_val = 0;
         p.descs.push_back(d);
         if (p.groups.empty() || key(order[(size_t)k]) != p.groups.back().fk * 2 + p.groups.back().dump)
-            p.groups.push_back({f.f_kind, f.leaf_llr ? 1 : 0, k, 0, (int)f.log2n, LaunchCfg{}});
+            p.groups.push_back({f.f_kind, f.leaf_llr ? 1 : 0, k, 0, (int)f.log2n, SizeHist{}, LaunchCfg{}});
         p.groups.back().count++;
+        p.groups.back().hist.add(f.log2n);
     }
     p.slots = 0;
     p.slot_bytes = 0;
+    int64_t frame_bytes = 0;  // per-frame slots: running offset
     for (auto& g : p.groups) {
-        g.cfg = group_cfg(c, g.fk, g.maxlog, g.count, g.dump != 0, plain);
-        if (force && !plain) {
-            g.cfg = *force;
-            if (g.dump || !c->prune) g.cfg.cutover = 12;
-            g.cfg.slots = std::max(1, std::min(g.cfg.slots, g.count));
-        }
+        g.cfg = group_cfg(c, g.fk, g.dump != 0, g.hist, plain, force);
+        int64_t per_wg = 0;
+        (void)group_slot_bytes(g.hist, g.cfg, p.per_frame, &per_wg);
         p.slots = std::max(p.slots, g.cfg.slots);
-        p.slot_bytes = std::max(p.slot_bytes, polar_dev_slot_bytes(g.maxlog, g.cfg.cutover));
+        p.slot_bytes = std::max(p.slot_bytes, per_wg);
+        if (p.per_frame)
+            for (int k = g.first; k < g.first + g.count; ++k)
+                if (p.descs[(size_t)k].log2n > g.cfg.cutover) {
+                    p.descs[(size_t)k].slot = reinterpret_cast<uint8_t*>((uintptr_t)frame_bytes);
+                    frame_bytes += polar_dev_slot_bytes(p.descs[(size_t)k].log2n, g.cfg.cutover);
+                }
     }
     p.desc_off = kHeaderBytes;
     p.slot_off = align256(p.desc_off + sizeof(FrameDesc) * (size_t)n_frames);
-    p.total = p.slot_off + (size_t)p.slots * (size_t)p.slot_bytes;
+    p.total = p.slot_off + (p.per_frame ? (size_t)frame_bytes : (size_t)p.slots * (size_t)p.slot_bytes);
 }
 
-namespace {
+// Descriptors of a plan bound to a workspace: per-frame slot offsets become
+// device pointers.
+void bind_descs(const Plan& p, void* ws, std::vector<FrameDesc>& out) {
+    out.assign(p.descs.begin(), p.descs.end());
+    if (!p.per_frame) return;
+    uint8_t* slots = (uint8_t*)ws + p.slot_off;
+    for (const auto& g : p.groups)
+        for (int k = g.first; k < g.first + g.count; ++k)
+            if (out[(size_t)k].log2n > g.cfg.cutover) out[(size_t)k].slot = slots + (uintptr_t)out[(size_t)k].slot;
+}
 
-int enqueue_launches(polar_ctx* c, const Plan& p, void* ws, hipStream_t s, bool plain) {
+int enqueue_launches(polar_ctx* c, const Plan& p, void* ws, hipStream_t s, bool plain, uint32_t* done) {
     uint8_t* base = (uint8_t*)ws;
     unsigned* counter = (unsigned*)base;
     const FrameDesc* dtab = (const FrameDesc*)(base + p.desc_off);
     uint8_t* slots = base + p.slot_off;
-    const int prune = plain ? 0 : c->prune;
     for (const auto& gr : p.groups) {
         DecodeLaunch a{};
         a.cutover = gr.cfg.cutover;
         a.fk = gr.fk;
-        a.prune = prune;
+        a.prune = plain ? 0 : gr.cfg.prune;
         a.dump = gr.dump;
         a.waves = gr.cfg.waves;
         a.counter = counter;
         a.slots = slots;
         a.slot_bytes = p.slot_bytes;
         a.prof = c->prof;
+        a.done = done;
         a.stream = s;
+        // frames above the cutover come first (longest first); the rest go
+        // to the per-wavefront kernel
+        int n_big = 0;
+        while (n_big < gr.count && p.descs[(size_t)(gr.first + n_big)].log2n > gr.cfg.cutover) ++n_big;
         if (plain) {
             for (int k = 0; k < gr.count; ++k) {
                 a.descs = dtab + gr.first + k;
                 a.n_frames = 1;
                 a.grid = 1;
+                a.small = k >= n_big;
+                a.small_log2n = p.descs[(size_t)(gr.first + k)].log2n;
+                a.fwg = 1;
                 hipError_t e = polar_dev_launch_decode(&a);
                 if (e != hipSuccess) return hip_fail(e, "decode launch");
             }
-        } else {
+            continue;
+        }
+        if (n_big > 0) {
             a.descs = dtab + gr.first;
-            a.n_frames = gr.count;
+            a.n_frames = n_big;
             a.grid = gr.cfg.slots;
+            a.small = 0;
             hipError_t e = polar_dev_launch_decode(&a);
             if (e != hipSuccess) return hip_fail(e, "decode launch");
+        }
+        if (n_big < gr.count) {
+            a.descs = dtab + gr.first + n_big;
+            a.n_frames = gr.count - n_big;
+            a.grid = gr.cfg.small_slots;
+            a.small = 1;
+            a.small_log2n = p.descs[(size_t)(gr.first + n_big)].log2n;
+            a.fwg = gr.cfg.fwg;
+            hipError_t e = polar_dev_launch_decode(&a);
+            if (e != hipSuccess) return hip_fail(e, "decode launch (per-wavefront frames)");
         }
     }
     return ok();
 }
+
+namespace {
 
 uint64_t fnv1a(const std::vector<uint8_t>& v) {
     uint64_t h = 1469598103934665603ull;
@@ -345,20 +484,23 @@ void put(std::vector<uint8_t>& v, const T& x) {
 // decode launch] per group, captured once for these exact descriptors,
 // launch parameters and workspace.
 int run_graph(polar_ctx* c, const Plan& p, void* ws, hipStream_t s) {
+    std::vector<FrameDesc> descs;
+    bind_descs(p, ws, descs);
     std::vector<uint8_t> key;
     put(key, ws);
     put(key, c->prof);
-    put(key, c->prune);
     for (const auto& g : p.groups) {
+        put(key, g.cfg.prune);
         put(key, g.first);
         put(key, g.count);
         put(key, g.cfg.cutover);
         put(key, g.cfg.waves);
         put(key, g.cfg.slots);
+        put(key, g.cfg.fwg);
     }
     put(key, p.slot_bytes);
-    const uint8_t* d = reinterpret_cast<const uint8_t*>(p.descs.data());
-    key.insert(key.end(), d, d + p.descs.size() * sizeof(FrameDesc));
+    const uint8_t* d = reinterpret_cast<const uint8_t*>(descs.data());
+    key.insert(key.end(), d, d + descs.size() * sizeof(FrameDesc));
     const uint64_t h = fnv1a(key);
     auto it = c->graphs.find(h);
     if (it != c->graphs.end() && it->second.key != key) {
@@ -388,10 +530,10 @@ int run_graph(polar_ctx* c, const Plan& p, void* ws, hipStream_t s) {
         }
         GraphEntry ge;
         ge.key = key;
-        const size_t nb = p.descs.size() * sizeof(FrameDesc);
+        const size_t nb = descs.size() * sizeof(FrameDesc);
         hipError_t e = hipHostMalloc((void**)&ge.pinned, std::max(nb, (size_t)64), hipHostMallocDefault);
         if (e != hipSuccess) return hip_fail(e, "pinned graph descriptors");
-        std::memcpy(ge.pinned, p.descs.data(), nb);
+        std::memcpy(ge.pinned, descs.data(), nb);
         hipStream_t cs = c->capture_stream;
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
@@ -399,7 +541,7 @@ int run_graph(polar_ctx* c, const Plan& p, void* ws, hipStream_t s) {
             return hip_fail(e, "begin graph capture");
         }
         e = hipMemcpyAsync((uint8_t*)ws + p.desc_off, ge.pinned, nb, hipMemcpyHostToDevice, cs);
-        int rc = e == hipSuccess ? enqueue_launches(c, p, ws, cs, false) : hip_fail(e, "captured copy");
+        int rc = e == hipSuccess ? enqueue_launches(c, p, ws, cs, false, nullptr) : hip_fail(e, "captured copy");
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         if (rc == POLAR_OK && e2 != hipSuccess) rc = hip_fail(e2, "end graph capture");
@@ -422,13 +564,16 @@ int run_graph(polar_ctx* c, const Plan& p, void* ws, hipStream_t s) {
 
 }  // namespace
 
-int run_plan(polar_ctx* c, const Plan& p, void* ws, size_t ws_bytes, hipStream_t s, Stager& st, bool plain) {
+int run_plan(polar_ctx* c, const Plan& p, void* ws, size_t ws_bytes, hipStream_t s, Stager& st, bool plain,
+             uint32_t* done) {
     if (!ws || ws_bytes < p.total)
         return fail(POLAR_E_NOMEM, "workspace of %zu bytes < %zu required", ws ? ws_bytes : (size_t)0, p.total);
     if (((uintptr_t)ws & 255) != 0) return fail(POLAR_E_INVAL, "workspace must be 256-byte aligned");
-    int rc = st.upload(p.descs.data(), p.descs.size(), (uint8_t*)ws + p.desc_off, s);
+    std::vector<FrameDesc> descs;
+    bind_descs(p, ws, descs);
+    int rc = st.upload(descs.data(), descs.size(), (uint8_t*)ws + p.desc_off, s);
     if (rc) return rc;
-    return enqueue_launches(c, p, ws, s, plain);
+    return enqueue_launches(c, p, ws, s, plain, done);
 }
 
 int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* stream, bool plain) {
@@ -523,6 +668,10 @@ extern "C" int polar_ctx_set_option(polar_ctx* c, int option, int64_t value) {
             if (value != 0 && value != 1) return fail(POLAR_E_INVAL, "graph must be 0 or 1");
             c->graph = (int)value;
             return ok();
+        case POLAR_OPT_FWG:
+            if (value < 0 || value > 8) return fail(POLAR_E_INVAL, "frames per workgroup must be 0 .. 8");
+            c->fwg = (int)value;
+            return ok();
         default:
             return fail(POLAR_E_INVAL, "unknown option %d", option);
     }
@@ -537,6 +686,7 @@ extern "C" int polar_ctx_get_option(polar_ctx* c, int option, int64_t* value) {
         case POLAR_OPT_MAX_SLOTS: *value = c->max_slots; return ok();
         case POLAR_OPT_TIMING: *value = (int64_t)(uintptr_t)c->prof; return ok();
         case POLAR_OPT_GRAPH: *value = c->graph; return ok();
+        case POLAR_OPT_FWG: *value = c->fwg; return ok();
         default: return fail(POLAR_E_INVAL, "unknown option %d", option);
     }
 }

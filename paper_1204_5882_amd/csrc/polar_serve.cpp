@@ -1,16 +1,25 @@
 // libpolar serving loop: requests (one frame each) are admitted against a
 // device arena, gathered into batches and decoded by the persistent batch
 // decoder on up to kStreams streams at once, so that new requests start while
-// earlier batches finish (continuous batching at batch granularity).
+// earlier batches still run (continuous batching).
 //
 // Admission: a batch takes requests from the head of the queue in arrival
-// order while its workspace (descriptors + per-frame scratch, see
-// polar_workspace_bytes) fits a free range of the arena; a request that
-// cannot fit even an empty arena completes with POLAR_E_NOMEM.  Latency is
-// measured on the host from submit to the poll that sees the batch finished.
+// order while its workspace fits a free range of the arena.  Each request is
+// charged its own footprint: a descriptor and a scratch slot sized for its
+// own N (per-frame slots), so admission follows the frames' sizes, not the
+// largest frame of the batch.  A request that cannot fit even an empty arena
+// completes with POLAR_E_NOMEM.
+//
+// Completion is per request: the decoder writes a ticket into a
+// host-coherent flag once the frame's u-hat is globally visible, and a poll
+// that finds the ticket completes the request, even while the rest of its
+// batch is still decoding.  A batch's arena range is released when its
+// stream event fires.  Latency is host time from submit to that poll.
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <deque>
 #include <thread>
@@ -35,12 +44,16 @@ struct Req {
     uint64_t id;
     polar_frame f;
     double t_submit;
+    uint32_t flag = 0xffffffffu;  // completion flag index while running
+    uint32_t ticket = 0;
+    bool finished = false;
 };
 
 struct Batch {
     bool active = false;
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;    // the batch's work has finished
+    hipEvent_t inputs = nullptr;  // inputs produced on the caller's stream
     Stager stager;
     size_t off = 0, bytes = 0;
     std::vector<Req> reqs;
@@ -54,9 +67,13 @@ struct polar_server {
     size_t arena_bytes = 0;
     int max_batch = 0;
     int poll_us = 50;
+    hipStream_t input_stream = nullptr;
     std::deque<Req> queue;
     Batch batch[kStreams];
     std::vector<polar_completion> ready;
+    uint32_t* flags = nullptr;  // host-coherent completion flags, one per running request
+    std::vector<uint32_t> free_flags;
+    uint32_t ticket = 0;
 };
 
 namespace {
@@ -82,33 +99,30 @@ bool arena_find(const polar_server* s, size_t need, size_t* off) {
     return false;
 }
 
-// Workspace of a growing batch, the same total make_plan computes, updated
-// per added frame without re-planning.
+// Workspace of a growing batch with per-frame slots: the same total
+// make_plan computes, kept per launch group so that adding a frame costs no
+// re-planning.
 struct BatchSize {
-    struct G { int count = 0, maxlog = 0; };
-    G g[4];  // f_kind * 2 + leaf dump
+    SizeHist g[4];  // f_kind * 2 + leaf dump
     int n = 0;
-    size_t total_with(const polar_ctx* c, const polar_frame& f) const {
-        G h[4];
-        for (int k = 0; k < 4; ++k) h[k] = g[k];
-        const int key = f.f_kind * 2 + (f.leaf_llr ? 1 : 0);
-        h[key].count++;
-        h[key].maxlog = std::max(h[key].maxlog, (int)f.log2n);
-        int slots = 0;
-        int64_t slot_bytes = 0;
+    static int key(const polar_frame& f) { return f.f_kind * 2 + (f.leaf_llr ? 1 : 0); }
+    size_t total(const polar_ctx* c, const SizeHist* h, int nf) const {
+        int64_t slots = 0;
         for (int k = 0; k < 4; ++k) {
             if (!h[k].count) continue;
-            const LaunchCfg cfg = group_cfg(c, k >> 1, h[k].maxlog, h[k].count, (k & 1) != 0, false);
-            slots = std::max(slots, cfg.slots);
-            slot_bytes = std::max(slot_bytes, polar_dev_slot_bytes(h[k].maxlog, cfg.cutover));
+            const LaunchCfg cfg = group_cfg(c, k >> 1, (k & 1) != 0, h[k], false);
+            slots += group_slot_bytes(h[k], cfg, true, nullptr);
         }
-        const size_t slot_off = align256(256 + sizeof(FrameDesc) * (size_t)(n + 1));
-        return slot_off + (size_t)slots * (size_t)slot_bytes;
+        return align256(256 + sizeof(FrameDesc) * (size_t)nf) + (size_t)slots;
+    }
+    size_t total_with(const polar_ctx* c, const polar_frame& f) const {
+        SizeHist h[4];
+        for (int k = 0; k < 4; ++k) h[k] = g[k];
+        h[key(f)].add(f.log2n);
+        return total(c, h, n + 1);
     }
     void add(const polar_frame& f) {
-        const int key = f.f_kind * 2 + (f.leaf_llr ? 1 : 0);
-        g[key].count++;
-        g[key].maxlog = std::max(g[key].maxlog, (int)f.log2n);
+        g[key(f)].add(f.log2n);
         ++n;
     }
 };
@@ -121,19 +135,38 @@ void complete(polar_server* s, uint64_t id, int status, double t_submit) {
     s->ready.push_back(c);
 }
 
-// Collect finished batches.
+void finish_req(polar_server* s, Req& r, int status) {
+    if (r.finished) return;
+    r.finished = true;
+    complete(s, r.id, status, r.t_submit);
+}
+
+void release_batch(polar_server* s, Batch& b) {
+    for (const auto& r : b.reqs)
+        if (r.flag != 0xffffffffu) s->free_flags.push_back(r.flag);
+    b.reqs.clear();
+    b.active = false;
+}
+
+// Complete requests whose frames are done, and collect finished batches.
+// Every batch is examined; the first device error is returned after all of
+// them have been reported with their own status.
 int reap(polar_server* s) {
+    int rc = POLAR_OK;
     for (auto& b : s->batch) {
         if (!b.active) continue;
+        for (auto& r : b.reqs)
+            if (!r.finished && r.flag != 0xffffffffu &&
+                __atomic_load_n(s->flags + r.flag, __ATOMIC_ACQUIRE) == r.ticket)
+                finish_req(s, r, POLAR_OK);
         hipError_t e = hipEventQuery(b.done);
         if (e == hipErrorNotReady) continue;
         const int status = e == hipSuccess ? POLAR_OK : POLAR_E_DEVICE;
-        for (const auto& r : b.reqs) complete(s, r.id, status, r.t_submit);
-        b.reqs.clear();
-        b.active = false;
-        if (e != hipSuccess) return hip_fail(e, "serving batch");
+        for (auto& r : b.reqs) finish_req(s, r, status);
+        release_batch(s, b);
+        if (e != hipSuccess && rc == POLAR_OK) rc = hip_fail(e, "serving batch");
     }
-    return ok();
+    return rc;
 }
 
 // Start batches on idle streams while requests wait and fit.
@@ -163,8 +196,9 @@ int launch(polar_server* s) {
         BatchSize bs;
         size_t need = 0, off = 0;
         int take = 0;
+        const int limit = std::min<int>(s->max_batch, (int)s->free_flags.size());
         for (const auto& r : s->queue) {
-            if (take >= s->max_batch) break;
+            if (take >= limit) break;
             const size_t nb = bs.total_with(c, r.f);
             if (nb > free_max) break;
             bs.add(r.f);
@@ -175,23 +209,36 @@ int launch(polar_server* s) {
         if (take == 0) break;  // the head waits for memory
         if (!arena_find(s, need, &off)) break;
         Plan p;
-        make_plan(c, fr.data(), take, false, p);
-        int rc = run_plan(c, p, s->arena + off, need, b.stream, b.stager, false);
+        make_plan(c, fr.data(), take, false, p, nullptr, true);
+        std::vector<Req> reqs(s->queue.begin(), s->queue.begin() + take);
+        for (size_t k = 0; k < p.descs.size(); ++k) {
+            Req& r = reqs[(size_t)p.order[k]];
+            r.flag = s->free_flags.back();
+            s->free_flags.pop_back();
+            if (++s->ticket == 0) ++s->ticket;
+            r.ticket = s->ticket;
+            p.descs[k].done_idx = r.flag;
+            p.descs[k].done_val = r.ticket;
+        }
+        // the batch starts after the work already enqueued on the input stream
+        hipError_t e = hipEventRecord(b.inputs, s->input_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.inputs, 0);
+        int rc = e == hipSuccess ? run_plan(c, p, s->arena + off, need, b.stream, b.stager, false, s->flags)
+                                 : hip_fail(e, "serving input dependency");
         if (rc) {
-            for (int k = 0; k < take; ++k) {
-                complete(s, s->queue.front().id, rc, s->queue.front().t_submit);
-                s->queue.pop_front();
+            for (auto& r : reqs) {
+                if (r.flag != 0xffffffffu) s->free_flags.push_back(r.flag);
+                complete(s, r.id, rc, r.t_submit);
             }
+            s->queue.erase(s->queue.begin(), s->queue.begin() + take);
             return rc;
         }
-        hipError_t e = hipEventRecord(b.done, b.stream);
+        e = hipEventRecord(b.done, b.stream);
         b.active = true;
         b.off = off;
         b.bytes = need;
-        for (int k = 0; k < take; ++k) {
-            b.reqs.push_back(s->queue.front());
-            s->queue.pop_front();
-        }
+        b.reqs = std::move(reqs);
+        s->queue.erase(s->queue.begin(), s->queue.begin() + take);
         if (e != hipSuccess) return hip_fail(e, "serving event");
     }
     return ok();
@@ -212,11 +259,23 @@ extern "C" int polar_serve_open(polar_ctx* c, const polar_serve_cfg* cfg, polar_
     s->ctx = c;
     s->arena = (uint8_t*)cfg->arena;
     s->arena_bytes = cfg->arena_bytes;
-    s->max_batch = cfg->max_slots ? cfg->max_slots : 2 * c->n_cu;
+    // default batch: the workgroups of the default decoder that can be resident at once
+    s->max_batch = cfg->max_slots ? cfg->max_slots : c->n_cu * occupancy(c, 12, 0, false, 8, true);
     s->poll_us = cfg->poll_us;
+    s->input_stream = (hipStream_t)cfg->input_stream;
+    const size_t n_flags = (size_t)s->max_batch * kStreams;
+    hipError_t e = hipHostMalloc((void**)&s->flags, n_flags * sizeof(uint32_t), hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        s->flags = nullptr;
+        polar_serve_close(s);
+        return hip_fail(e, "serving completion flags");
+    }
+    for (size_t i = 0; i < n_flags; ++i) s->flags[i] = 0;
+    for (size_t i = n_flags; i-- > 0;) s->free_flags.push_back((uint32_t)i);
     for (auto& b : s->batch) {
-        hipError_t e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
+        e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b.inputs, hipEventDisableTiming);
         if (e != hipSuccess) {
             polar_serve_close(s);
             return hip_fail(e, "serving streams");
@@ -231,7 +290,11 @@ extern "C" int polar_serve_submit(polar_server* s, const polar_frame* req, uint6
     int rc = validate_frames(req, 1);
     if (rc) return rc;
     if (s->queue.size() >= kQueueCap) return fail(POLAR_E_BUSY, "serving queue full (%zu requests)", kQueueCap);
-    s->queue.push_back({req_id, *req, now_s()});
+    Req r;
+    r.id = req_id;
+    r.f = *req;
+    r.t_submit = now_s();
+    s->queue.push_back(r);
     return ok();
 }
 
@@ -252,10 +315,25 @@ extern "C" int polar_serve_poll(polar_server* s, polar_completion* out, int max_
 extern "C" int polar_serve_pending(const polar_server* s, int* queued, int* running, int* completed) {
     if (!s) return fail(POLAR_E_INVAL, "NULL server");
     int run = 0;
-    for (const auto& b : s->batch) run += (int)b.reqs.size();
+    for (const auto& b : s->batch)
+        for (const auto& r : b.reqs) run += r.finished ? 0 : 1;
     if (queued) *queued = (int)s->queue.size();
     if (running) *running = run;
     if (completed) *completed = (int)s->ready.size();
+    return ok();
+}
+
+extern "C" int polar_serve_stats(const polar_server* s, int* batches_running, size_t* arena_used) {
+    if (!s) return fail(POLAR_E_INVAL, "NULL server");
+    int nb = 0;
+    size_t used = 0;
+    for (const auto& b : s->batch)
+        if (b.active) {
+            ++nb;
+            used += b.bytes;
+        }
+    if (batches_running) *batches_running = nb;
+    if (arena_used) *arena_used = used;
     return ok();
 }
 
@@ -270,7 +348,8 @@ extern "C" int polar_serve_cancel(polar_server* s, uint64_t req_id) {
     }
     for (const auto& b : s->batch)
         for (const auto& r : b.reqs)
-            if (r.id == req_id) return fail(POLAR_E_BUSY, "request %llu is already running", (unsigned long long)req_id);
+            if (r.id == req_id && !r.finished)
+                return fail(POLAR_E_BUSY, "request %llu is already running", (unsigned long long)req_id);
     return fail(POLAR_E_INVAL, "request %llu is not queued", (unsigned long long)req_id);
 }
 
@@ -286,8 +365,10 @@ extern "C" int polar_serve_close(polar_server* s) {
             }
             b.stager.release();
             if (b.done) (void)hipEventDestroy(b.done);
+            if (b.inputs) (void)hipEventDestroy(b.inputs);
             if (b.stream) (void)hipStreamDestroy(b.stream);
         }
+        if (s->flags) (void)hipHostFree(s->flags);
     }
     delete s;
     return rc;
@@ -324,19 +405,30 @@ extern "C" int polar_serve(polar_ctx* c, const polar_serve_cfg* cfg, polar_next_
         progressed |= n > 0;
         int q = 0, run = 0, fin = 0;
         (void)polar_serve_pending(s, &q, &run, &fin);
-        if (ended && q == 0 && run == 0 && fin == 0) break;
+        if (ended && q == 0 && run == 0 && fin == 0) {
+            int nb = 0;
+            (void)polar_serve_stats(s, &nb, nullptr);
+            if (nb == 0) break;  // every request reported and every batch's range released
+        }
         if (!progressed && s->poll_us > 0) std::this_thread::sleep_for(std::chrono::microseconds(s->poll_us));
     }
-    // a device error ends the loop: report what is left
+    // A device error ends the loop.  Requests still on the device are reported
+    // only after their batch has stopped touching their buffers.
     if (rc) {
-        int n = 0;
         for (auto& b : s->batch) {
-            for (const auto& r : b.reqs) done(user, r.id, rc, now_s() - r.t_submit);
-            b.reqs.clear();
+            if (!b.active) continue;
+            const hipError_t e = hipEventSynchronize(b.done);
+            for (auto& r : b.reqs)
+                if (!r.finished) {
+                    r.finished = true;
+                    done(user, r.id, e == hipSuccess ? POLAR_OK : rc, now_s() - r.t_submit);
+                }
+            release_batch(s, b);
         }
+        for (const auto& r : s->ready) done(user, r.req_id, r.status, r.latency_s);
+        s->ready.clear();
         for (const auto& r : s->queue) done(user, r.id, POLAR_E_CANCELLED, now_s() - r.t_submit);
         s->queue.clear();
-        (void)n;
     }
     const int rc2 = polar_serve_close(s);
     return rc ? rc : rc2;

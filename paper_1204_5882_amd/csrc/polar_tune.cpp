@@ -63,7 +63,8 @@ int time_candidate(polar_ctx* c, const polar_frame* frames, int n_frames, const 
 }  // namespace
 
 extern "C" int polar_autotune(polar_ctx* c, const polar_frame* frames, int n_frames, int reps, void* stream,
-                              int* best_cutover, int* best_waves, int* best_slots, double* best_ms) {
+                              int* best_cutover, int* best_waves, int* best_slots, int* best_fwg, int* best_prune,
+                              double* best_ms, int* n_candidates) {
     if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
     int rc = validate_frames(frames, n_frames);
     if (rc) return rc;
@@ -81,23 +82,51 @@ extern "C" int polar_autotune(polar_ctx* c, const polar_frame* frames, int n_fra
     if (!g.ok) return fail(POLAR_E_DEVICE, "cannot select device %d", c->device);
     hipStream_t s = (hipStream_t)stream;
 
+    SizeHist hist;
+    for (int i = 0; i < n_frames; ++i) hist.add(frames[i].log2n);
     std::vector<LaunchCfg> grid;
-    const int slot_opts[] = {c->n_cu, 2 * c->n_cu, 3 * c->n_cu};
-    for (int cut = 10; cut <= 12; ++cut) {
+    auto push = [&](const LaunchCfg& cfg) {
+        for (const auto& q : grid)
+            if (q.cutover == cfg.cutover && q.waves == cfg.waves && q.slots == cfg.slots && q.fwg == cfg.fwg &&
+                q.prune == cfg.prune)
+                return;
+        grid.push_back(cfg);
+    };
+    for (int cut = 8; cut <= 12; ++cut) {
         if (!polar_dev_cutover_supported(cut)) continue;
+        int lg_small = 0, n_small = 0;
+        for (int l = 1; l <= cut; ++l)
+            if (hist.n[l]) {
+                lg_small = l;
+                n_small += hist.n[l];
+            }
         for (int w : {4, 8}) {
             if (!polar_dev_waves_supported(w)) continue;
-            for (int sl : slot_opts) {
-                LaunchCfg cfg;
-                cfg.cutover = cut;
-                cfg.waves = w;
-                cfg.slots = std::min(sl, n_frames);
-                bool dup = false;
-                for (const auto& q : grid)
-                    dup |= q.cutover == cfg.cutover && q.waves == cfg.waves && q.slots == cfg.slots;
-                if (!dup) grid.push_back(cfg);
+            const int cap = c->n_cu * occupancy(c, cut, fk, false, w, true);
+            const int f_max = n_small ? polar_dev_max_fwg(cut, lg_small, w) : 1;
+            for (int sl : {c->n_cu / 2, c->n_cu, cap}) {
+                if (sl < 1 || sl > cap) continue;
+                for (int fw : {1, 2, 4, 8}) {
+                    if (fw > f_max) continue;
+                    LaunchCfg cfg;
+                    cfg.cutover = cut;
+                    cfg.waves = w;
+                    cfg.slots = sl;
+                    cfg.fwg = fw;
+                    cfg.prune = 1;
+                    push(cfg);
+                }
             }
         }
+    }
+    {  // the unpruned decoder (same results, every node visited)
+        LaunchCfg cfg;
+        cfg.cutover = 12;
+        cfg.waves = 8;
+        cfg.slots = c->n_cu * occupancy(c, 12, fk, false, 8, false);
+        cfg.fwg = 1;
+        cfg.prune = 0;
+        push(cfg);
     }
     Candidate best;
     bool have = false;
@@ -113,26 +142,33 @@ extern "C" int polar_autotune(polar_ctx* c, const polar_frame* frames, int n_fra
         }
     }
     if (!have) return fail(POLAR_E_NOMEM, "no candidate configuration fits the workspace");
-    LaunchCfg keep = best.cfg;
-    if (keep.slots >= n_frames) keep.slots = std::max(keep.slots, 2 * c->n_cu);  // not limited by this batch
-    c->tuned[{fk, maxlog}] = keep;
-    if (best_cutover) *best_cutover = best.cfg.cutover;
-    if (best_waves) *best_waves = best.cfg.waves;
-    if (best_slots) *best_slots = best.cfg.slots;
+    c->tuned[{fk, maxlog}] = best.cfg;
+    // what a batch of these frames now runs with (workgroups capped by the batch)
+    const LaunchCfg used = group_cfg(c, fk, false, hist, false, &best.cfg);
+    if (best_cutover) *best_cutover = used.cutover;
+    if (best_waves) *best_waves = used.waves;
+    if (best_slots) *best_slots = used.slots;
+    if (best_fwg) *best_fwg = used.fwg;
+    if (best_prune) *best_prune = used.prune;
     if (best_ms) *best_ms = best.median_ms;
+    if (n_candidates) *n_candidates = (int)grid.size();
     return ok();
 }
 
 extern "C" int polar_query_launch(const polar_ctx* c, int f_kind, int log2n, int n_frames, int* cutover,
-                                  int* waves, int* slots) {
+                                  int* waves, int* slots, int* fwg, int* prune) {
     if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
     if (log2n < 1 || log2n > POLAR_MAX_LOG2N) return fail(POLAR_E_INVAL, "log2n %d outside 1..%d", log2n, POLAR_MAX_LOG2N);
     if (f_kind != POLAR_F_MINSUM && f_kind != POLAR_F_BOXPLUS) return fail(POLAR_E_INVAL, "unknown f_kind");
     if (n_frames < 1) return fail(POLAR_E_INVAL, "n_frames < 1");
-    const LaunchCfg cfg = group_cfg(c, f_kind, log2n, n_frames, false, false);
+    SizeHist h;
+    for (int i = 0; i < n_frames; ++i) h.add(log2n);
+    const LaunchCfg cfg = group_cfg(c, f_kind, false, h, false);
     if (cutover) *cutover = cfg.cutover;
     if (waves) *waves = cfg.waves;
     if (slots) *slots = cfg.slots;
+    if (fwg) *fwg = cfg.fwg;
+    if (prune) *prune = cfg.prune;
     return ok();
 }
 
@@ -149,9 +185,11 @@ extern "C" int polar_tune_save(const polar_ctx* c, const char* path) {
     std::fprintf(f, "{\"libpolar_tune\": 1, \"entries\": [");
     bool first = true;
     for (const auto& kv : c->tuned) {
-        std::fprintf(f, "%s\n  {\"f_kind\": %d, \"log2n\": %d, \"cutover\": %d, \"waves\": %d, \"slots\": %d}",
+        std::fprintf(f,
+                     "%s\n  {\"f_kind\": %d, \"log2n\": %d, \"cutover\": %d, \"waves\": %d, \"slots\": %d, "
+                     "\"fwg\": %d, \"prune\": %d}",
                      first ? "" : ",", kv.first.first, kv.first.second, kv.second.cutover, kv.second.waves,
-                     kv.second.slots);
+                     kv.second.slots, kv.second.fwg, kv.second.prune);
         first = false;
     }
     std::fprintf(f, "\n]}\n");
@@ -196,17 +234,22 @@ extern "C" int polar_tune_load(polar_ctx* c, const char* path) {
         const size_t b = text.find('}', a);
         if (b == std::string::npos) return fail(POLAR_E_INVAL, "%s: unterminated entry", path);
         const std::string obj = text.substr(a, b - a + 1);
-        long fk, lg, cut, w, sl;
+        long fk, lg, cut, w, sl, fw = 0, pr = -1;
         if (!read_int(obj, "f_kind", &fk) || !read_int(obj, "log2n", &lg) || !read_int(obj, "cutover", &cut) ||
             !read_int(obj, "waves", &w) || !read_int(obj, "slots", &sl))
             return fail(POLAR_E_INVAL, "%s: entry lacks a field", path);
+        (void)read_int(obj, "fwg", &fw);    // optional
+        (void)read_int(obj, "prune", &pr);  // optional
         if ((fk != POLAR_F_MINSUM && fk != POLAR_F_BOXPLUS) || lg < 1 || lg > POLAR_MAX_LOG2N ||
-            !polar_dev_cutover_supported((int)cut) || !polar_dev_waves_supported((int)w) || sl < 1 || sl > (1 << 20))
+            !polar_dev_cutover_supported((int)cut) || !polar_dev_waves_supported((int)w) || sl < 1 ||
+            sl > (1 << 20) || fw < 0 || fw > w || pr < -1 || pr > 1 || (pr == 0 && cut != 12))
             return fail(POLAR_E_INVAL, "%s: entry out of range", path);
         LaunchCfg cfg;
         cfg.cutover = (int)cut;
         cfg.waves = (int)w;
         cfg.slots = (int)sl;
+        cfg.fwg = (int)fw;
+        cfg.prune = (int)pr;
         table[{(int)fk, (int)lg}] = cfg;
         pos = b + 1;
     }

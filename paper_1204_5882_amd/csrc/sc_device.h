@@ -15,7 +15,9 @@ struct FrameDesc {
     float* leaf;
     int32_t log2n;
     int32_t fkind;
-    int64_t pad[2];
+    uint8_t* slot;      // the frame's own scratch slot, or null: the workgroup's slot
+    uint32_t done_idx;  // completion flag index (with DecodeLaunch::done), or ~0u
+    uint32_t done_val;  // value written to done[done_idx] once the frame's u-hat is out
 };
 static_assert(sizeof(FrameDesc) == 64, "descriptor layout");
 
@@ -33,6 +35,10 @@ struct DecodeLaunch {
     uint8_t* slots;            // per-workgroup scratch, slot_bytes each
     int64_t slot_bytes;
     unsigned long long* prof;  // optional timing counters (device, 8 words) or null
+    uint32_t* done;            // completion flags (host-coherent memory) or null
+    int small;                 // 1: every frame has at most 2^cutover leaves (per-wavefront kernel)
+    int small_log2n;           // small: log2 N of the largest (first) frame
+    int fwg;                   // small: frames per workgroup = its wavefronts
     hipStream_t stream;
 };
 
@@ -51,8 +57,36 @@ hipError_t polar_dec_c11_ms_prune(const DecodeLaunch* a);
 hipError_t polar_dec_c11_bp_prune(const DecodeLaunch* a);
 hipError_t polar_dec_c10_ms_prune(const DecodeLaunch* a);
 hipError_t polar_dec_c10_bp_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c9_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c9_bp_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c8_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c8_bp_prune(const DecodeLaunch* a);
+int polar_dec_c12_ms_occupancy(int waves, int small_log2n);
+int polar_dec_c12_ms_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c12_ms_prune_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_bp_occupancy(int waves, int small_log2n);
+int polar_dec_c12_bp_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_bp_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c12_bp_prune_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c11_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c11_bp_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c10_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c10_bp_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c9_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c9_bp_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c8_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c8_bp_prune_occupancy(int waves, int small_log2n);
 
 int polar_dev_cutover_supported(int c);
+// Frames per workgroup a workgroup of `waves` wavefronts can decode at once,
+// one per wavefront, for frames of 2^log2n <= 2^cutover leaves (LDS bound).
+int polar_dev_max_fwg(int cutover, int log2n, int waves);
+// Resident workgroups per compute unit for a decoder variant (0 on error):
+// its large-frame kernel with `waves` wavefronts (small_log2n < 0), or its
+// per-wavefront kernel with `waves` wavefronts for frames of at most
+// 2^small_log2n leaves.
+int polar_dev_occupancy(int cutover, int fk, int prune, int dump, int waves, int small_log2n);
 int polar_dev_waves_supported(int w);
 int64_t polar_dev_slot_bytes(int log2n, int cutover);
 hipError_t polar_dev_encode(int log2n, int n_frames, const uint32_t* u, uint32_t* x, hipStream_t s);

@@ -109,11 +109,66 @@ extern "C" hipError_t polar_dev_launch_decode(const DecodeLaunch* a) {
             if (v == 2) return polar_dec_c10_ms_prune(a);
             if (v == 6) return polar_dec_c10_bp_prune(a);
             break;
+        case 9:
+            if (v == 2) return polar_dec_c9_ms_prune(a);
+            if (v == 6) return polar_dec_c9_bp_prune(a);
+            break;
+        case 8:
+            if (v == 2) return polar_dec_c8_ms_prune(a);
+            if (v == 6) return polar_dec_c8_bp_prune(a);
+            break;
     }
     return hipErrorInvalidValue;
 }
 
-extern "C" int polar_dev_cutover_supported(int c) { return c >= 10 && c <= 12; }
+extern "C" int polar_dev_occupancy(int cutover, int fk, int prune, int dump, int waves, int small_log2n) {
+    const int v = (fk ? 4 : 0) + (prune ? 2 : 0) + (dump ? 1 : 0);
+    switch (cutover) {
+        case 12:
+            switch (v) {
+                case 0: return polar_dec_c12_ms_occupancy(waves, small_log2n);
+                case 1: return polar_dec_c12_ms_dump_occupancy(waves, small_log2n);
+                case 2: return polar_dec_c12_ms_prune_occupancy(waves, small_log2n);
+                case 3: return polar_dec_c12_ms_prune_dump_occupancy(waves, small_log2n);
+                case 4: return polar_dec_c12_bp_occupancy(waves, small_log2n);
+                case 5: return polar_dec_c12_bp_dump_occupancy(waves, small_log2n);
+                case 6: return polar_dec_c12_bp_prune_occupancy(waves, small_log2n);
+                case 7: return polar_dec_c12_bp_prune_dump_occupancy(waves, small_log2n);
+            }
+            break;
+        case 11:
+            if (v == 2) return polar_dec_c11_ms_prune_occupancy(waves, small_log2n);
+            if (v == 6) return polar_dec_c11_bp_prune_occupancy(waves, small_log2n);
+            break;
+        case 10:
+            if (v == 2) return polar_dec_c10_ms_prune_occupancy(waves, small_log2n);
+            if (v == 6) return polar_dec_c10_bp_prune_occupancy(waves, small_log2n);
+            break;
+        case 9:
+            if (v == 2) return polar_dec_c9_ms_prune_occupancy(waves, small_log2n);
+            if (v == 6) return polar_dec_c9_bp_prune_occupancy(waves, small_log2n);
+            break;
+        case 8:
+            if (v == 2) return polar_dec_c8_ms_prune_occupancy(waves, small_log2n);
+            if (v == 6) return polar_dec_c8_bp_prune_occupancy(waves, small_log2n);
+            break;
+    }
+    return 0;
+}
+
+extern "C" int polar_dev_max_fwg(int cutover, int log2n, int waves) {
+    if (log2n > cutover) return 1;
+    switch (cutover) {
+        case 12: return max_fwg<12>(log2n, waves);
+        case 11: return max_fwg<11>(log2n, waves);
+        case 10: return max_fwg<10>(log2n, waves);
+        case 9: return max_fwg<9>(log2n, waves);
+        case 8: return max_fwg<8>(log2n, waves);
+    }
+    return 1;
+}
+
+extern "C" int polar_dev_cutover_supported(int c) { return c >= 8 && c <= 12; }
 extern "C" int polar_dev_waves_supported(int w) { return w == 4 || w == 8; }
 
 extern "C" int64_t polar_dev_slot_bytes(int log2n, int cutover) {

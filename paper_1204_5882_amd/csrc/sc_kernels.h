@@ -652,14 +652,18 @@ __device__ __forceinline__ void blk_init(Blk& B, uint64_t F, uint64_t V) {
 template <int C>
 struct SubCfg {
     static constexpr int R = C < 9 ? C : 9;  // highest register level
-    // LDS offset (floats) of level L > R: level C at 0, then C-1, ...
-    static constexpr int off(int L) { return (1 << (C + 1)) - (1 << (L + 1)); }
-    static constexpr int lds_floats = (1 << (C + 1)) - (1 << (R + 1));
+    // LDS floats a subtree of 2^lg leaves keeps its levels above R in: level
+    // L (R < L <= lg) at offset 2^(lg+1) - 2^(L+1) from the subtree's base,
+    // so the subtree's own input level sits at the base.
+    __host__ __device__ static constexpr int floats(int lg) { return lg > R ? (1 << (lg + 1)) - (1 << (R + 1)) : 0; }
+    __host__ __device__ static constexpr int off(int lg, int L) { return (1 << (lg + 1)) - (1 << (L + 1)); }
+    static constexpr int lds_floats = floats(C);
+    static constexpr int NL = C > R ? C - R : 1;  // LDS-resident levels
 };
 
 template <int C>
 struct Lv {
-    float* lds;
+    float* lp[SubCfg<C>::NL];  // level L > R at lp[L - R - 1] (wave-uniform)
     float a9[8];
     float a8[4];
     float a7[2];
@@ -668,7 +672,7 @@ struct Lv {
 
 template <int L, int C>
 __device__ __forceinline__ float lv_get(Lv<C>& v, int k) {
-    if constexpr (L > SubCfg<C>::R) return v.lds[SubCfg<C>::off(L) + k * 64 + lane_id()];
+    if constexpr (L > SubCfg<C>::R) return v.lp[L - SubCfg<C>::R - 1][k * 64 + lane_id()];
     else if constexpr (L == 9) return v.a9[k];
     else if constexpr (L == 8) return v.a8[k];
     else if constexpr (L == 7) return v.a7[k];
@@ -677,7 +681,7 @@ __device__ __forceinline__ float lv_get(Lv<C>& v, int k) {
 
 template <int L, int C>
 __device__ __forceinline__ void lv_set(Lv<C>& v, int k, float x) {
-    if constexpr (L > SubCfg<C>::R) v.lds[SubCfg<C>::off(L) + k * 64 + lane_id()] = x;
+    if constexpr (L > SubCfg<C>::R) v.lp[L - SubCfg<C>::R - 1][k * 64 + lane_id()] = x;
     else if constexpr (L == 9) v.a9[k] = x;
     else if constexpr (L == 8) v.a8[k] = x;
     else if constexpr (L == 7) v.a7[k] = x;
@@ -814,14 +818,16 @@ __device__ __forceinline__ void emit_uhat(uint64_t acc, int nb, uint32_t* uhat) 
 }
 
 // Decode a subtree of 2^lg leaves, 6 <= lg <= C, on one wavefront.  Input
-// LLRs: at lds + SubCfg<C>::off(lg) when lg > R, else at gsrc (global).
+// LLRs: at lds (the subtree's LDS base) when lg > R, else at gsrc (global).
 template <int C, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void subtree_decode(const SubIO io, int lg, float* lds, const float* gsrc) {
     constexpr int R = SubCfg<C>::R;
     const int l = lane_id();
     const int nb = 1 << (lg - 6);  // 64-leaf blocks
     Lv<C> v;
-    v.lds = lds;
+#pragma unroll
+    for (int L = R + 1; L <= C; ++L)  // levels above lg are never touched
+        v.lp[L - R - 1] = lds + (L <= lg ? SubCfg<C>::off(lg, L) : 0);
 
     SubCtx x;
     // Block words: lane l holds block l's mask and values.
@@ -1035,33 +1041,15 @@ __host__ __device__ inline int64_t slot_level_offset(int log2n, int d) {
 // time spent in register-resident subtree decoding.
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
+// A frame of 2^n > 2^C leaves, decoded by the whole workgroup: sweeps over
+// the levels above the cutover, one wavefront per subtree.
 template <int C, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot, float* lds, float* tier,
                                              uint32_t* words, uint64_t* lbeta, uint64_t& sub_ticks) {
     const int W = (int)(blockDim.x >> 6);  // wavefronts in the workgroup
-    constexpr int R = SubCfg<C>::R;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps sweep offsets scalar
-    const int n = fd.log2n;
-    if (n < 6) {
-        if (wave == 0) tiny_decode<FK, PRUNE, DUMP>(fd);
-        return;
-    }
-    if (n <= C) {
-        // the whole frame is one subtree
-        if (n > R) {
-            float* dst = lds + SubCfg<C>::off(n);
-            for (int i = tid; i < (1 << n); i += W * 64) dst[i] = fd.llr[i];
-            __syncthreads();
-        }
-        if (wave == 0) {
-            const uint64_t t0 = now_ticks();
-            SubIO io{fd.mask, fd.vals, fd.uhat, fd.leaf, nullptr, nullptr};
-            subtree_decode<C, FK, PRUNE, DUMP>(io, n, lds, fd.llr);
-            sub_ticks += now_ticks() - t0;
-        }
-        return;
-    }
+    const int n = fd.log2n;  // > C: frames of at most 2^C leaves go to decode_small
     const int D = n - C;
     const int64_t N = (int64_t)1 << n;
     uint64_t* beta = reinterpret_cast<uint64_t*>(slot + slot_level_offset(n, D));
@@ -1127,7 +1115,9 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
             const int64_t base = s << C;
             SubIO io{words + (s & 1) * 2 * NW, words + (s & 1) * 2 * NW + NW, nullptr,
                      DUMP ? fd.leaf + base : nullptr, beta + s * 64, lbeta + (s & 1) * 64};
-            subtree_decode<C, FK, PRUNE, DUMP>(io, C, lds, nullptr);
+            // (a cutover node that fits the registers is loaded from LDS
+            // through a generic pointer)
+            subtree_decode<C, FK, PRUNE, DUMP>(io, C, lds, C <= SubCfg<C>::R ? lds : nullptr);
             sub_ticks += now_ticks() - t0;
         } else if (wave == 1 && s + 1 < nsub) {
             stage(s + 1);
@@ -1144,18 +1134,72 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
 template <int C>
 constexpr int TIER_FLOATS = (2 << C) + (4 << C);
 
+// All LDS LLR storage of a workgroup: the subtree levels of a large frame,
+// then its tier; or, for frames of at most 2^C leaves, one region per
+// wavefront decoding its own frame.
+template <int C>
+constexpr int LDS_FLOATS = (SubCfg<C>::lds_floats > (1 << C) ? SubCfg<C>::lds_floats : (1 << C)) + TIER_FLOATS<C>;
+
+// Frames of 2^lg <= 2^C leaves one workgroup of W wavefronts decodes at once
+// (one per wavefront), bounded by the LDS their subtree levels need.
+template <int C>
+__host__ __device__ inline int max_fwg(int lg, int W) {
+    const int need = SubCfg<C>::floats(lg);
+    const int by_lds = need > 0 ? LDS_FLOATS<C> / need : W;
+    return by_lds < W ? by_lds : W;
+}
+
+// Completion flag of a frame: written (system scope, host-coherent memory)
+// once every u-hat word of the frame is globally visible.  Call with the
+// whole wavefront active; lane 0 stores.
+__device__ __forceinline__ void signal_done(const FrameDesc& fd, uint32_t* done) {
+    if (done == nullptr || fd.done_idx == 0xffffffffu) return;
+    __threadfence_system();
+    if (lane_id() == 0) __hip_atomic_store(done + fd.done_idx, fd.done_val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// A frame of 2^n <= 2^C leaves decoded by one wavefront on its own LDS
+// region (no workgroup barrier).  The channel LLRs are staged in the
+// region's input level by the lane that later reads each element.
+template <int C, int FK, bool PRUNE, bool DUMP>
+__device__ __forceinline__ void decode_small(const FrameDesc& fd, float* lds) {
+    constexpr int R = SubCfg<C>::R;
+    const int n = fd.log2n;
+    if (n < 6) {
+        tiny_decode<FK, PRUNE, DUMP>(fd);
+        return;
+    }
+    if (n > R)
+        for (int i = lane_id(); i < (1 << n); i += 64) lds[i] = fd.llr[i];
+    SubIO io{fd.mask, fd.vals, fd.uhat, fd.leaf, nullptr, nullptr};
+    subtree_decode<C, FK, PRUNE, DUMP>(io, n, lds, fd.llr);
+}
+
+// Next frame index from the work counter, for one wavefront.
+__device__ __forceinline__ int wave_draw(unsigned* counter) {
+    unsigned f = 0;
+    if (lane_id() == 0) f = atomicAdd(counter, 1u);
+    return (int)__builtin_amdgcn_readfirstlane(f);
+}
+
 // One kernel serves every workgroup size up to MAXW wavefronts (its register
-// budget is the one of MAXW).
+// budget is the one of MAXW).  Workgroups take frames from a device counter
+// in the host's order (longest first); every frame has more than 2^C leaves
+// (smaller ones go to k_sc_decode_small) and is decoded by the whole
+// workgroup.
 template <int C, int FK, bool PRUNE, bool DUMP, int MAXW>
 __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __restrict__ descs, int n_frames,
                                                        unsigned* __restrict__ counter, uint8_t* slots,
-                                                       int64_t slot_bytes, unsigned long long* prof) {
-    __shared__ float lds[SubCfg<C>::lds_floats > (1 << C) ? SubCfg<C>::lds_floats : (1 << C)];
-    __shared__ float tier[TIER_FLOATS<C>];  // LLR levels of sizes 2^(C+1) and 2^(C+2)
+                                                       int64_t slot_bytes, unsigned long long* prof,
+                                                       uint32_t* done) {
+    __shared__ float lds_all[LDS_FLOATS<C>];
     __shared__ int s_frame;
     __shared__ uint32_t s_words[2][2 << (C - 5)];  // staged mask and value words of the next subtree
     __shared__ uint64_t s_beta[2][64];  // partial sums of the last two subtrees (slot s & 1)
-    uint8_t* slot = slots + (int64_t)blockIdx.x * slot_bytes;
+    constexpr int LDS_SUB = LDS_FLOATS<C> - TIER_FLOATS<C>;
+    float* lds = lds_all;
+    float* tier = lds_all + LDS_SUB;  // LLR levels of sizes 2^(C+1) and 2^(C+2)
+    uint8_t* wg_slot = slots + (int64_t)blockIdx.x * slot_bytes;
     while (true) {
         if (threadIdx.x == 0) s_frame = (int)atomicAdd(counter, 1u);
         __syncthreads();
@@ -1163,13 +1207,43 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __rest
         __syncthreads();
         if (f >= n_frames) break;
         const FrameDesc fd = descs[f];
+        if (fd.log2n <= C) continue;  // never sent here by the host
         uint64_t sub_ticks = 0;
         const uint64_t t0 = prof ? now_ticks() : 0;
-        decode_frame<C, FK, PRUNE, DUMP>(fd, slot, lds, tier, &s_words[0][0], &s_beta[0][0], sub_ticks);
+        decode_frame<C, FK, PRUNE, DUMP>(fd, fd.slot ? fd.slot : wg_slot, lds, tier, &s_words[0][0], &s_beta[0][0],
+                                         sub_ticks);
         __syncthreads();
+        if (threadIdx.x < 64) signal_done(fd, done);
         if (prof && threadIdx.x == 0) {
             atomicAdd(prof + 0, (unsigned long long)sub_ticks);
             atomicAdd(prof + 1, (unsigned long long)(now_ticks() - t0));
+            atomicAdd(prof + 2, 1ull);
+        }
+    }
+}
+
+// Frames of at most 2^C leaves: each wavefront of a workgroup (fwg of them)
+// decodes frames on its own (its own LDS region, no workgroup barrier),
+// drawing them from the device counter one at a time.  region: LDS floats
+// per wavefront, for the largest frame of the launch (frames come longest
+// first, so later frames fit too); the launch gives fwg * region floats of
+// dynamic LDS.
+template <int C, int FK, bool PRUNE, bool DUMP, int MAXW>
+__global__ __launch_bounds__(MAXW * 64) void k_sc_decode_small(const FrameDesc* __restrict__ descs, int n_frames,
+                                                             unsigned* __restrict__ counter,
+                                                             unsigned long long* prof, uint32_t* done, int region) {
+    extern __shared__ float lds_dyn[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    float* mine = lds_dyn + wave * region;
+    for (int g = wave_draw(counter); g < n_frames; g = wave_draw(counter)) {
+        const FrameDesc d = descs[g];
+        const uint64_t t0 = prof ? now_ticks() : 0;
+        decode_small<C, FK, PRUNE, DUMP>(d, mine);
+        signal_done(d, done);
+        if (prof && lane_id() == 0) {
+            const unsigned long long dt = now_ticks() - t0;
+            atomicAdd(prof + 0, dt);
+            atomicAdd(prof + 1, dt);
             atomicAdd(prof + 2, 1ull);
         }
     }
@@ -1190,16 +1264,56 @@ hipError_t launch_decode(const DecodeLaunch& a) {
     if (a.waves < 1 || a.waves > MAXW) return hipErrorInvalidValue;
     const int waves = a.waves;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, a.stream, a.counter);
-    hipLaunchKernelGGL((k_sc_decode<C, FK, PRUNE, DUMP, MAXW>), dim3(a.grid), dim3(waves * 64), 0, a.stream,
-                       a.descs, a.n_frames, a.counter, a.slots, a.slot_bytes, a.prof);
+    if (a.small) {
+        // every frame of the launch has at most 2^C leaves, the first one the
+        // most; one wavefront per frame in flight, each with its LDS region
+        const int region = SubCfg<C>::floats(a.small_log2n);
+        if (a.small_log2n > C || a.fwg < 1 || a.fwg > MAXW || a.fwg * region > LDS_FLOATS<C>)
+            return hipErrorInvalidValue;
+        const size_t smem = (size_t)a.fwg * (size_t)region * sizeof(float);
+        auto kern = k_sc_decode_small<C, FK, PRUNE, DUMP, MAXW>;
+        if (smem > 65536) {
+            const hipError_t e =
+                hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3(a.grid), dim3(a.fwg * 64), smem, a.stream, a.descs, a.n_frames, a.counter,
+                           a.prof, a.done, region);
+    } else {
+        hipLaunchKernelGGL((k_sc_decode<C, FK, PRUNE, DUMP, MAXW>), dim3(a.grid), dim3(waves * 64), 0, a.stream,
+                           a.descs, a.n_frames, a.counter, a.slots, a.slot_bytes, a.prof, a.done);
+    }
     return hipGetLastError();
+}
+
+// Resident workgroups per compute unit: the large-frame kernel with `waves`
+// wavefronts (small_log2n < 0), or the per-wavefront kernel with `waves`
+// wavefronts decoding frames of at most 2^small_log2n leaves.
+template <int C, int FK, bool PRUNE, bool DUMP>
+int occupancy_decode(int waves, int small_log2n) {
+    int blocks = 0;
+    hipError_t e;
+    if (small_log2n >= 0) {
+        const size_t smem = (size_t)waves * (size_t)SubCfg<C>::floats(small_log2n < C ? small_log2n : C) * 4;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sc_decode_small<C, FK, PRUNE, DUMP, MAX_WAVES>,
+                                                         waves * 64, smem);
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sc_decode<C, FK, PRUNE, DUMP, MAX_WAVES>,
+                                                         waves * 64, 0);
+    }
+    return e == hipSuccess ? blocks : 0;
 }
 
 }  // namespace polar_dev
 
 // One translation unit per decoder variant, so that the variants compile in
-// parallel: NAME launches k_sc_decode<C, FK, PRUNE, DUMP>.
+// parallel: NAME launches k_sc_decode<C, FK, PRUNE, DUMP>; NAME_occupancy
+// reports the resident workgroups per compute unit of its large-frame (small
+// = 0) or per-wavefront (small = 1) kernel.
 #define POLAR_DECODE_VARIANT(NAME, C, FK, PRUNE, DUMP)                                  \
     extern "C" hipError_t NAME(const DecodeLaunch* a) {                                \
         return polar_dev::launch_decode<C, FK, PRUNE, DUMP>(*a);                       \
+    }                                                                                  \
+    extern "C" int NAME##_occupancy(int waves, int small_log2n) {                      \
+        return polar_dev::occupancy_decode<C, FK, PRUNE, DUMP>(waves, small_log2n);    \
     }

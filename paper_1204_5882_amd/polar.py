@@ -35,6 +35,7 @@ POLAR_OPT_WG_WAVES = 3
 POLAR_OPT_MAX_SLOTS = 4
 POLAR_OPT_TIMING = 5
 POLAR_OPT_GRAPH = 6
+POLAR_OPT_FWG = 7
 
 # every symbol declared in include/polar.h
 EXPORTED = [
@@ -43,8 +44,8 @@ EXPORTED = [
     "polar_ctx_get_option", "polar_workspace_bytes", "polar_sc_decode_batch",
     "polar_sc_decode_plain", "polar_autotune", "polar_query_launch", "polar_tune_clear",
     "polar_tune_save", "polar_tune_load", "polar_serve_open", "polar_serve_submit", "polar_serve_poll",
-    "polar_serve_pending", "polar_serve_cancel", "polar_serve_close", "polar_serve",
-    "polar_debug_lane_selftest",
+    "polar_serve_pending", "polar_serve_stats", "polar_serve_cancel", "polar_serve_close", "polar_serve",
+    "polar_debug_lane_selftest", "polar_fer_generate_bsc", "polar_fer_workspace_bytes", "polar_fer_bsc",
 ]
 
 
@@ -72,6 +73,29 @@ class polar_serve_cfg(ctypes.Structure):
         ("arena", ctypes.c_void_p),
         ("max_slots", ctypes.c_int),
         ("poll_us", ctypes.c_int),
+        ("input_stream", ctypes.c_void_p),
+    ]
+
+
+class polar_fer_cfg(ctypes.Structure):
+    _fields_ = [
+        ("log2n", ctypes.c_int32),
+        ("f_kind", ctypes.c_int32),
+        ("p", ctypes.c_double),
+        ("frozen_mask", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64),
+        ("frame0", ctypes.c_int64),
+        ("n_frames", ctypes.c_int64),
+        ("batch", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class polar_fer_result(ctypes.Structure):
+    _fields_ = [
+        ("frames", ctypes.c_int64),
+        ("frame_errors", ctypes.c_int64),
+        ("bit_errors", ctypes.c_int64),
     ]
 
 
@@ -113,8 +137,8 @@ def load():
         "polar_workspace_bytes": ([P, P, I], SZ),
         "polar_sc_decode_batch": ([P, P, I, P], I),
         "polar_sc_decode_plain": ([P, P, I, P], I),
-        "polar_autotune": ([P, P, I, I, P, P, P, P, P], I),
-        "polar_query_launch": ([P, I, I, I, P, P, P], I),
+        "polar_autotune": ([P, P, I, I, P, P, P, P, P, P, P, P], I),
+        "polar_query_launch": ([P, I, I, I, P, P, P, P, P], I),
         "polar_tune_clear": ([P], I),
         "polar_tune_save": ([P, ctypes.c_char_p], I),
         "polar_tune_load": ([P, ctypes.c_char_p], I),
@@ -122,10 +146,14 @@ def load():
         "polar_serve_submit": ([P, P, ctypes.c_uint64], I),
         "polar_serve_poll": ([P, P, I, P], I),
         "polar_serve_pending": ([P, P, P, P], I),
+        "polar_serve_stats": ([P, P, P], I),
         "polar_serve_cancel": ([P, ctypes.c_uint64], I),
         "polar_serve_close": ([P], I),
         "polar_serve": ([P, P, NEXT_FN, DONE_FN, P], I),
         "polar_debug_lane_selftest": ([P, P], I),
+        "polar_fer_generate_bsc": ([I, ctypes.c_double, P, ctypes.c_uint64, I64, I, P, P, P, P, P], I),
+        "polar_fer_workspace_bytes": ([P, P], SZ),
+        "polar_fer_bsc": ([P, P, P, SZ, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -191,6 +219,24 @@ def encode(log2n: int, u, x=None, n_frames: Optional[int] = None, stream=None):
         raise ValueError("buffers too small")
     _check(load().polar_encode(int(log2n), int(n_frames), _ptr(u), _ptr(x), _stream_handle(stream)))
     return x
+
+
+def fer_generate_bsc(log2n: int, p: float, frozen_mask, seed: int, frame0: int, n_frames: int, stream=None):
+    """Synthetic BSC frames on the device (the harness's generator): returns
+    (u words, frozen-value words, LLRs) as torch tensors of shapes
+    (n_frames, W), (n_frames, W), (n_frames, N)."""
+    import torch
+
+    dev = frozen_mask.device
+    w = n_words(log2n)
+    u = torch.empty((n_frames, w), dtype=torch.int32, device=dev)
+    vals = torch.empty_like(u)
+    x = torch.empty_like(u)
+    llr = torch.empty((n_frames, 1 << log2n), dtype=torch.float32, device=dev)
+    _check(load().polar_fer_generate_bsc(int(log2n), float(p), _ptr(frozen_mask), int(seed), int(frame0),
+                                         int(n_frames), _ptr(u), _ptr(vals), _ptr(x), _ptr(llr),
+                                         _stream_handle(stream)))
+    return u, vals, llr
 
 
 def lane_selftest(stream=None):
@@ -269,6 +315,25 @@ class Ctx:
     def decode_batch(self, frames: ctypes.Array, n: int, stream=None):
         _check(self._lib.polar_sc_decode_batch(self._h, frames, int(n), _stream_handle(stream)))
 
+    def fer_bsc(self, log2n: int, p: float, frozen_mask, n_frames: int, seed: int = 1, frame0: int = 0,
+                f_kind: int = POLAR_F_MINSUM, batch: int = 0, stream=None):
+        """Monte-Carlo FER on BSC(p), everything on the device.  Returns
+        (result dict, per-frame bit errors as a torch int32 tensor)."""
+        import torch
+
+        cfg = polar_fer_cfg(int(log2n), int(f_kind), float(p), _ptr(frozen_mask), int(seed), int(frame0),
+                            int(n_frames), int(batch), 0)
+        need = self._lib.polar_fer_workspace_bytes(self._h, ctypes.addressof(cfg))
+        if need == 0:
+            raise PolarError(POLAR_E_INVAL, "invalid FER configuration")
+        ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        bit_err = torch.empty(max(1, int(n_frames)), dtype=torch.int32, device=f"cuda:{self.device}")
+        res = polar_fer_result()
+        _check(self._lib.polar_fer_bsc(self._h, ctypes.addressof(cfg), _ptr(ws), need, _ptr(bit_err),
+                                       ctypes.addressof(res), _stream_handle(stream)))
+        return ({"frames": res.frames, "frame_errors": res.frame_errors, "bit_errors": res.bit_errors},
+                bit_err[: int(n_frames)])
+
     def decode_plain(self, frames: ctypes.Array, n: int, stream=None):
         _check(self._lib.polar_sc_decode_plain(self._h, frames, int(n), _stream_handle(stream)))
 
@@ -281,32 +346,40 @@ class Ctx:
     # autotuner -----------------------------------------------------------
     def autotune(self, items: Sequence[dict], reps: int = 3, stream=None) -> dict:
         """Time the built launch configurations on these frames, keep the best
-        for their (f_kind, largest log2n); returns it."""
+        for their (f_kind, largest log2n); returns the launch a batch of these
+        frames now gets."""
         import torch
 
         items = list(items)
         frames = make_frames(items)
-        # room for the largest candidate (3 frames in flight per compute unit)
+        # room for the largest candidate (every resident workgroup, any cutover)
         need = 0
-        for cut in (10, 11, 12):
-            self.set_option(POLAR_OPT_CUTOVER, cut)
-            self.set_option(POLAR_OPT_MAX_SLOTS, 3 * torch.cuda.get_device_properties(self.device).multi_processor_count)
-            need = max(need, self.workspace_bytes(frames, len(items)))
-        self.set_option(POLAR_OPT_CUTOVER, 0)
-        self.set_option(POLAR_OPT_MAX_SLOTS, 0)
+        saved = {o: self.get_option(o) for o in (POLAR_OPT_CUTOVER, POLAR_OPT_MAX_SLOTS, POLAR_OPT_WG_WAVES)}
+        for cut in (8, 9, 10, 11, 12):
+            for waves in (4, 8):
+                self.set_option(POLAR_OPT_CUTOVER, cut)
+                self.set_option(POLAR_OPT_WG_WAVES, waves)
+                self.set_option(POLAR_OPT_MAX_SLOTS, 1 << 20)
+                need = max(need, self.workspace_bytes(frames, len(items)))
+        for o, v in saved.items():
+            self.set_option(o, v)
         if self.workspace is None or self.workspace.numel() < need:
             self.set_workspace(torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}"))
-        c, w, sl, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        c, w, sl, fw, pr, n = (ctypes.c_int() for _ in range(6))
+        ms = ctypes.c_double()
         _check(self._lib.polar_autotune(self._h, frames, len(items), int(reps), _stream_handle(stream),
                                         ctypes.addressof(c), ctypes.addressof(w), ctypes.addressof(sl),
-                                        ctypes.addressof(ms)))
-        return {"cutover": c.value, "waves": w.value, "slots": sl.value, "median_ms": ms.value}
+                                        ctypes.addressof(fw), ctypes.addressof(pr), ctypes.addressof(ms),
+                                        ctypes.addressof(n)))
+        return {"cutover": c.value, "waves": w.value, "slots": sl.value, "fwg": fw.value, "prune": pr.value,
+                "median_ms": ms.value, "candidates": n.value}
 
     def query_launch(self, f_kind: int, log2n: int, n_frames: int) -> dict:
-        c, w, sl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        c, w, sl, fw, pr = (ctypes.c_int() for _ in range(5))
         _check(self._lib.polar_query_launch(self._h, int(f_kind), int(log2n), int(n_frames), ctypes.addressof(c),
-                                            ctypes.addressof(w), ctypes.addressof(sl)))
-        return {"cutover": c.value, "waves": w.value, "slots": sl.value}
+                                            ctypes.addressof(w), ctypes.addressof(sl), ctypes.addressof(fw),
+                                            ctypes.addressof(pr)))
+        return {"cutover": c.value, "waves": w.value, "slots": sl.value, "fwg": fw.value, "prune": pr.value}
 
     def tune_clear(self):
         _check(self._lib.polar_tune_clear(self._h))
@@ -323,12 +396,15 @@ class Server:
     uint8 tensor).  Frames are dicts as for make_frames; the tensors must stay
     alive until their request completes (the server keeps a reference)."""
 
-    def __init__(self, ctx: Ctx, arena, max_slots: int = 0, poll_us: int = 50):
+    def __init__(self, ctx: Ctx, arena, max_slots: int = 0, poll_us: int = 50, input_stream=None):
+        """input_stream: the stream request inputs are produced on (default:
+        torch's current stream); every batch waits for the work enqueued on it."""
         self._lib = load()
         self.ctx = ctx
         self.arena = arena
         self._h = ctypes.c_void_p()
-        cfg = polar_serve_cfg(arena.numel() * arena.element_size(), _ptr(arena), int(max_slots), int(poll_us))
+        cfg = polar_serve_cfg(arena.numel() * arena.element_size(), _ptr(arena), int(max_slots), int(poll_us),
+                              _stream_handle(input_stream))
         _check(self._lib.polar_serve_open(ctx._h, ctypes.addressof(cfg), ctypes.addressof(self._h)))
         self._keep = {}
         self._buf = (polar_completion * 1024)()
@@ -355,6 +431,12 @@ class Server:
         _check(self._lib.polar_serve_pending(self._h, ctypes.addressof(q), ctypes.addressof(r), ctypes.addressof(c)))
         return q.value, r.value, c.value
 
+    def stats(self) -> tuple:
+        """(batches on the device, arena bytes they hold)."""
+        nb, used = ctypes.c_int(), ctypes.c_size_t()
+        _check(self._lib.polar_serve_stats(self._h, ctypes.addressof(nb), ctypes.addressof(used)))
+        return nb.value, used.value
+
     def cancel(self, req_id: int) -> int:
         """POLAR_OK, or the error code (POLAR_E_BUSY if running, POLAR_E_INVAL if unknown)."""
         return int(self._lib.polar_serve_cancel(self._h, int(req_id)))
@@ -373,7 +455,7 @@ class Server:
             pass
 
 
-def serve(ctx: Ctx, arena, next_request, on_done, max_slots: int = 0, poll_us: int = 50):
+def serve(ctx: Ctx, arena, next_request, on_done, max_slots: int = 0, poll_us: int = 50, input_stream=None):
     """Blocking serving loop.  next_request() -> (item, req_id) | None (none
     yet) | StopIteration-like sentinel "end"; on_done(req_id, status, latency_s)."""
     lib = load()
@@ -399,5 +481,6 @@ def serve(ctx: Ctx, arena, next_request, on_done, max_slots: int = 0, poll_us: i
         on_done(int(rid), int(status), float(lat))
 
     nf, df = NEXT_FN(_next), DONE_FN(_done)
-    cfg = polar_serve_cfg(arena.numel() * arena.element_size(), _ptr(arena), int(max_slots), int(poll_us))
+    cfg = polar_serve_cfg(arena.numel() * arena.element_size(), _ptr(arena), int(max_slots), int(poll_us),
+                          _stream_handle(input_stream))
     _check(lib.polar_serve(ctx._h, ctypes.addressof(cfg), nf, df, None))

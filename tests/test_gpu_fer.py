@@ -1,0 +1,89 @@
+"""GPU parity of the FER harness (NEXT: frame error rate and efficiency,
+Table 1): the device generator builds exactly the frames the oracle's
+generator builds (u, frozen values, LLRs bit for bit), and the device
+harness (generate, decode, count) reports exactly the per-frame bit errors
+of the oracle's SC decoder on those frames (FP32 min-sum is bit-exact)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import fer
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_5882_amd import polar as lp
+
+    lp.load()
+
+
+def _mask_dev(mask):
+    import torch
+
+    return torch.from_numpy(synth.pack_bits(mask).view(np.int32).copy()).cuda()
+
+
+@pytest.mark.parametrize("log2n", [1, 3, 5, 6, 7, 12, 16, 20])
+def test_device_generator_equals_oracle_generator(log2n):
+    import torch
+
+    from paper_1204_5882_amd import polar as lp
+
+    p = 0.03
+    n = 1 << log2n
+    mask, _, _ = oracle.frozen_set(log2n, synth.bsc_z0(p), n // 4)
+    frames = 3 if log2n >= 16 else 9
+    _say(f"case: generator log2n={log2n}")
+    u, vals, llr = lp.fer_generate_bsc(log2n, p, _mask_dev(mask), seed=77, frame0=1000, n_frames=frames)
+    torch.cuda.synchronize()
+    u, vals, llr = u.cpu().numpy().view(np.uint32), vals.cpu().numpy().view(np.uint32), llr.cpu().numpy()
+    for k in range(frames):
+        ou, ofv, ollr, _ = fer.bsc_frame(77, 1000 + k, log2n, p, mask)
+        assert np.array_equal(synth.unpack_bits(u[k], n), ou), k
+        assert np.array_equal(synth.unpack_bits(vals[k], n), ofv), k
+        assert np.array_equal(llr[k].view(np.uint32), ollr.view(np.uint32)), k
+        if log2n < 5:  # unused bits of the single word are zero
+            assert int(u[k][0]) >> n == 0
+
+
+@pytest.mark.parametrize("log2n,p,nf,frames,frame0", [
+    (4, 0.1, 8, 3000, 0),       # per-wavefront frames, many of them
+    (10, 0.02, 300, 2000, 5),
+    (12, 0.02, 819, 400, 0),    # the N = 2^12 BSC 2% code
+    (16, 0.02, 1 << 14, 48, 100),
+])
+def test_device_fer_equals_oracle_fer(log2n, p, nf, frames, frame0):
+    import torch
+
+    from paper_1204_5882_amd import polar as lp
+
+    mask, _, _ = oracle.frozen_set(log2n, synth.bsc_z0(p), nf)
+    ctx = lp.Ctx(0)
+    _say(f"case: device FER log2n={log2n} frames={frames}")
+    res, bit_err = ctx.fer_bsc(log2n, p, _mask_dev(mask), frames, seed=5, frame0=frame0, batch=frames // 3 + 1)
+    torch.cuda.synchronize()
+    got = bit_err.cpu().numpy().astype(np.int64)
+    errs, bits, flags = fer.fer_bsc(5, frame0, frames, log2n, p, mask)
+    assert res["frames"] == frames
+    assert res["frame_errors"] == errs, (res, errs)
+    assert res["bit_errors"] == bits, (res, bits)
+    assert np.array_equal((got > 0).astype(np.uint8), flags)
+    # the same run in one step (automatic batch) gives the same counts
+    res2, bit_err2 = ctx.fer_bsc(log2n, p, _mask_dev(mask), frames, seed=5, frame0=frame0)
+    torch.cuda.synchronize()
+    assert res2 == res and np.array_equal(bit_err2.cpu().numpy(), bit_err.cpu().numpy())
+    ctx.close()

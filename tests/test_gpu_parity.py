@@ -17,7 +17,8 @@ import pytest
 import oracle
 import synth
 
-from gpu_helpers import biawgn_frames, bsc_frames, decode, oracle_many
+from gpu_helpers import (biawgn_frames, bsc_frames, check_boxplus_decisions, check_boxplus_leaves, decode,
+                         oracle_many, random_frames)
 
 pytestmark = pytest.mark.gpu
 
@@ -93,27 +94,7 @@ def test_encode_matches_oracle(log2n):
 
 
 # ---------------------------------------------------------------- min-sum, every size
-def _random_frames(log2n, g, count):
-    n = 1 << log2n
-    frames = []
-    for k in range(count):
-        kind = k % 4
-        if kind == 0:
-            llr = np.where(g.random(n) < 0.1, -1.0, 1.0).astype(np.float32) * np.float32(3.47)
-        elif kind == 1:
-            llr = (2.0 * ((1 - 2 * g.integers(0, 2, n)) + 0.9 * g.standard_normal(n)) / 0.81).astype(np.float32)
-        elif kind == 2:
-            llr = g.integers(-2, 3, n).astype(np.float32)   # many exact zeros
-        else:
-            llr = (g.integers(-3, 4, n) * (0.5 + g.random(n))).astype(np.float32)
-        dens = [0.0, 1.0, 0.3, 0.5, 0.7][k % 5]
-        if k % 7 == 6:
-            mask, _, _ = oracle.frozen_set(log2n, 0.35, n // 2)
-        else:
-            mask = (g.random(n) < dens).astype(np.uint8)
-        fval = (g.integers(0, 2, n) & mask).astype(np.uint8)
-        frames.append((llr, mask, fval))
-    return frames
+_random_frames = random_frames
 
 
 @pytest.mark.parametrize("log2n", list(range(1, 17)))
@@ -247,42 +228,17 @@ def test_batching_invariance_mixed_sizes_and_rates():
 
 
 # ---------------------------------------------------------------- box-plus
-def _magnitude_scale(llr):
-    """S_i: leaf values with g -> |a| + |b| and f -> min(|a|, |b|)."""
-    n = llr.size
-    return oracle.sc_decode(np.abs(llr), np.ones(n, np.uint8), np.zeros(n, np.uint8), want_leaf=True)[1]
-
-
-def _check_boxplus(frames, us, leaves):
-    rescued = 0
-    for k, (fr, u, lf) in enumerate(zip(frames, us, leaves)):
-        llr, mask, fval = fr
-        u_or, l_ref, _ = oracle.sc_decode(llr, mask, fval, boxplus=True, teacher=u, want_leaf=True)
-        s = _magnitude_scale(llr).astype(np.float64)
-        err = np.abs(lf.astype(np.float64) - l_ref)
-        tol = 1e-5 * np.maximum(np.abs(l_ref), s)
-        bad = err > tol
-        assert not bad.any(), f"frame {k}: {bad.sum()} leaves out of tolerance, worst {err[bad].max()}"
-        rescued += int((err > 1e-5 * np.abs(l_ref)).sum())
-        dis = (u_or != u) & (mask == 0)
-        assert np.all(np.abs(l_ref[dis]) < 1e-6), f"frame {k}: decisions differ at |L| >= 1e-6"
-    return rescued
-
-
 @pytest.mark.parametrize("log2n", [1, 4, 6, 8, 11, 12, 13, 16])
 def test_boxplus_sizes_within_tolerance(log2n):
     frames = biawgn_frames(log2n, 0.97, (1 << log2n) - int(0.45 * (1 << log2n)),
                            [6000 + 10 * log2n + k for k in range(4)])
     _say(f"case: box-plus log2n={log2n} leaf dump")
     us, leaves = decode(frames, f_kind=1, prune=False, dump=True)
-    rescued = _check_boxplus(frames, us, leaves)
+    rescued = check_boxplus_leaves(frames, us, leaves, f"box-plus 2^{log2n}", strict=True)
     print(f"box-plus log2n={log2n}: {rescued} leaves within tolerance only through S_i")
     _say(f"case: box-plus log2n={log2n} pruned")
     up, _ = decode(frames, f_kind=1, prune=True)
-    for k, fr in enumerate(frames):
-        u_or, l_ref, _ = oracle.sc_decode(fr[0], fr[1], fr[2], boxplus=True, teacher=up[k], want_leaf=True)
-        dis = (u_or != up[k]) & (fr[1] == 0)
-        assert np.all(np.abs(l_ref[dis]) < 1e-6)
+    check_boxplus_decisions(frames, up, f"box-plus pruned 2^{log2n}", strict=True)
 
 
 def test_cfg3_n2p24_boxplus_sampled():
@@ -292,7 +248,7 @@ def test_cfg3_n2p24_boxplus_sampled():
     frames = biawgn_frames(log2n, 0.97, (1 << 24) - int(0.45 * (1 << 24)), [3000])
     _say("case: cfg3 N = 2^24 box-plus leaf dump")
     us, leaves = decode(frames, f_kind=1, prune=False, dump=True)
-    rescued = _check_boxplus(frames, us, leaves)
+    rescued = check_boxplus_leaves(frames, us, leaves, "cfg3 unpruned", strict=True)
     print(f"cfg3: {rescued} leaves within tolerance only through S_i")
 
 

@@ -56,7 +56,7 @@ def _mixed_frames(n_frames, lo, hi, seed):
 
 
 # ------------------------------------------------------------ launch variants
-@pytest.mark.parametrize("cut", [10, 11])
+@pytest.mark.parametrize("cut", [8, 9, 10, 11])
 def test_smaller_cutover_minsum_matches_oracle(cut):
     from paper_1204_5882_amd import polar as lp
 
@@ -69,9 +69,11 @@ def test_smaller_cutover_minsum_matches_oracle(cut):
             assert np.array_equal(us[k], refs[k]), (cut, waves, k)
 
 
-@pytest.mark.parametrize("cut", [10, 11])
+@pytest.mark.parametrize("cut", [8, 9, 10, 11])
 def test_smaller_cutover_boxplus_equals_cutover_12(cut):
-    """Box-plus results do not depend on where the HBM levels end."""
+    """Determinism: box-plus results do not depend on where the HBM levels
+    end (every f and g sees the same operands).  Agreement with the oracle is
+    checked in test_gpu_boxplus.py."""
     from paper_1204_5882_amd import polar as lp
 
     frames = biawgn_frames(15, 0.97, 18000, range(7200, 7204))
@@ -87,7 +89,7 @@ def test_large_frame_on_every_cutover():
 
     frames = bsc_frames(20, 0.03, 262144, [7300])
     ref = oracle.sc_decode(*frames[0])[0]
-    for cut in (10, 11, 12):
+    for cut in (8, 9, 10, 11, 12):
         _say(f"case: 2^20 min-sum, cutover {cut}")
         us, _ = decode(frames, opts={lp.POLAR_OPT_CUTOVER: cut})
         assert np.array_equal(us[0], ref), cut
@@ -142,10 +144,11 @@ def test_autotune_picks_a_built_config_and_keeps_results():
     items = frame_items(frames)
     _say("case: autotune 8 x 2^16")
     best = ctx.autotune(items, reps=2)
-    assert best["cutover"] in (10, 11, 12) and best["waves"] in (4, 8) and best["slots"] >= 1
-    assert best["median_ms"] > 0
+    assert best["cutover"] in (8, 9, 10, 11, 12) and best["waves"] in (4, 8) and best["slots"] >= 1
+    assert best["prune"] in (0, 1) and 1 <= best["fwg"] <= best["waves"]
+    assert best["median_ms"] > 0 and best["candidates"] > 20
     q = ctx.query_launch(0, 16, 8)
-    assert (q["cutover"], q["waves"]) == (best["cutover"], best["waves"])
+    assert {k: q[k] for k in ("cutover", "waves", "prune")} == {k: best[k] for k in ("cutover", "waves", "prune")}
     # other sizes keep the defaults
     assert ctx.query_launch(0, 18, 8)["cutover"] == 12
     for it in items:
@@ -171,7 +174,7 @@ def test_autotune_picks_a_built_config_and_keeps_results():
         assert ctx2.query_launch(0, 16, 8)["cutover"] == 12
         bad = os.path.join(d, "bad.json")
         with open(bad, "w") as f:
-            f.write('{"libpolar_tune": 1, "entries": [{"f_kind": 0, "log2n": 16, "cutover": 9, "waves": 4, "slots": 8}]}')
+            f.write('{"libpolar_tune": 1, "entries": [{"f_kind": 0, "log2n": 16, "cutover": 13, "waves": 4, "slots": 8}]}')
         with pytest.raises(lp.PolarError):
             ctx2.tune_load(bad)
         ctx2.close()
@@ -369,4 +372,158 @@ def test_blocking_serve_with_callbacks():
     for k, it in enumerate(items):
         assert results[500 + k][0] == lp.POLAR_OK
         assert np.array_equal(bits_host(it["u_hat"], it["llr"].numel()), refs[k]), k
+    ctx.close()
+
+
+# ------------------------------------------------ frames per workgroup (small N)
+@pytest.mark.parametrize("fwg", [1, 2, 4, 8])
+def test_small_frames_per_wavefront(fwg):
+    """Frames of at most 2^cutover leaves decoded one per wavefront, fwg per
+    workgroup, behind larger frames of the same launch (the workgroup drops
+    to per-wavefront mode when it reaches them): every frame equals the
+    oracle, at cutover 12 (LDS caps 2^12 frames at 4 per workgroup) and 10."""
+    from paper_1204_5882_amd import polar as lp
+
+    g = np.random.default_rng(1700 + fwg)
+    frames = []
+    for k in range(300):
+        log2n = int(g.integers(1, 13)) if k % 10 else int(g.integers(13, 16))
+        p = float(g.uniform(0.01, 0.05))
+        mask, _, _ = oracle.frozen_set(log2n, synth.bsc_z0(p), -1, 0.1)
+        _, fval, llr = synth.frame(90000 + 1000 * fwg + k, log2n, "bsc", p, mask, lambda v, n=log2n: oracle.encode(n, v))
+        frames.append((llr, mask, fval))
+    refs = [oracle.sc_decode(*fr)[0] for fr in frames]
+    for cut in (12, 10):
+        for waves in (4, 8):
+            if fwg > waves:
+                continue
+            _say(f"case: small frames fwg={fwg} cutover={cut} waves={waves}")
+            ctx = lp.Ctx(0)
+            us, _ = decode(frames, ctx=ctx, opts={lp.POLAR_OPT_FWG: fwg, lp.POLAR_OPT_CUTOVER: cut,
+                                                  lp.POLAR_OPT_WG_WAVES: waves, lp.POLAR_OPT_MAX_SLOTS: 24})
+            q = ctx.query_launch(0, cut, 300)   # frames of 2^cutover leaves
+            assert q["fwg"] == min(fwg, {12: 4, 10: 7}[cut], waves), q
+            ctx.close()
+            for k in range(len(frames)):
+                assert np.array_equal(us[k], refs[k]), (fwg, cut, waves, k)
+
+
+def test_small_frames_many_per_cu_boxplus_and_dump():
+    """Per-wavefront decoding with box-plus and with leaf dumps (2^6 .. 2^12)."""
+    from gpu_helpers import check_boxplus_decisions, random_frames
+
+    from paper_1204_5882_amd import polar as lp
+
+    g = np.random.default_rng(1800)
+    frames = []
+    for lg in (6, 9, 10, 11, 12):
+        frames += random_frames(lg, g, 12)
+    _say("case: per-wavefront box-plus, 60 frames")
+    us, _ = decode(frames, f_kind=1, opts={lp.POLAR_OPT_FWG: 8, lp.POLAR_OPT_MAX_SLOTS: 4})
+    check_boxplus_decisions(frames, us, "per-wavefront box-plus")
+    _say("case: per-wavefront min-sum with leaf dump")
+    us, leaves = decode(frames, prune=False, dump=True, opts={lp.POLAR_OPT_FWG: 8, lp.POLAR_OPT_MAX_SLOTS: 4})
+    for k, fr in enumerate(frames):
+        ref_u, ref_l, _ = oracle.sc_decode(*fr, want_leaf=True)
+        assert np.array_equal(us[k], ref_u), k
+        assert np.all(leaves[k] == ref_l), k
+
+
+def test_launch_respects_occupancy():
+    """Workgroups of a launch never exceed what can be resident at once."""
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    ctx = lp.Ctx(0)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    ctx.set_option(lp.POLAR_OPT_MAX_SLOTS, 1 << 20)
+    for cut in (8, 9, 10, 11, 12):
+        ctx.set_option(lp.POLAR_OPT_CUTOVER, cut)
+        q = ctx.query_launch(0, 20, 100000)
+        assert 1 <= q["slots"] <= 8 * n_cu, q
+        if cut == 12:  # about 127 KiB of LDS per workgroup: one per compute unit
+            assert q["slots"] == n_cu, q
+    ctx.close()
+
+
+def test_serving_two_batches_resident_and_per_request_completion():
+    """A batch of four 2^22 requests, then a batch of small requests on
+    another stream while the first still runs: both batches are on the
+    device at once, the small requests complete before the large ones (each
+    request completes when its own frame does), and every result equals the
+    oracle."""
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    big = bsc_frames(22, 0.03, 1 << 20, range(7900, 7904))
+    small = bsc_frames(14, 0.03, 4096, range(7910, 7926))
+    refs = oracle_many(big) + oracle_many(small)
+    ctx = lp.Ctx(0)
+    arena = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    srv = lp.Server(ctx, arena, poll_us=0)
+    items = frame_items(big) + frame_items(small)
+    _say("case: two resident batches")
+    for k in range(4):
+        srv.submit(items[k], k)
+    assert srv.poll() == []           # starts the 2^22 batch
+    for k in range(4, 20):
+        srv.submit(items[k], k)
+    done, order = {}, []
+    max_batches = 0
+    t0 = time.time()
+    while len(done) < 20:
+        for rid, st, lat in srv.poll():
+            done[rid] = (st, lat)
+            order.append(rid)
+        max_batches = max(max_batches, srv.stats()[0])
+        assert time.time() - t0 < 60, (done, srv.pending())
+    srv.close()
+    torch.cuda.synchronize()
+    assert max_batches == 2
+    assert all(done[k][0] == lp.POLAR_OK for k in range(20))
+    first_big = min(order.index(k) for k in range(4))
+    assert all(order.index(k) < first_big for k in range(4, 20)), order
+    assert max(done[k][1] for k in range(4, 20)) < min(done[k][1] for k in range(4))
+    for k, it in enumerate(items):
+        assert np.array_equal(bits_host(it["u_hat"], it["llr"].numel()), refs[k]), k
+    ctx.close()
+
+
+def test_serving_waits_for_inputs_on_the_input_stream():
+    """Inputs written on the caller's stream right before submit (no host
+    synchronisation): the batch must wait for them.  The LLR tensors are
+    filled on the stream after a long kernel, so a batch that did not wait
+    would read the stale values."""
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    frames = bsc_frames(16, 0.03, 16384, range(8000, 8008))
+    refs = oracle_many(frames)
+    ctx = lp.Ctx(0)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    items = frame_items(frames)
+    srv = lp.Server(ctx, arena, poll_us=0, input_stream=stream)
+    host = [torch.from_numpy(fr[0]).pin_memory() for fr in frames]
+    torch.cuda.synchronize()
+    _say("case: serving inputs produced on the input stream")
+    with torch.cuda.stream(stream):
+        for it in items:
+            it["llr"].fill_(1.0)            # wrong values, then the real ones
+        x = torch.randn(4096, 4096, device="cuda")
+        for _ in range(8):                  # keep the stream busy for a while
+            x = x @ x
+            x = x / x.norm()
+        for it, h in zip(items, host):
+            it["llr"].copy_(h, non_blocking=True)
+            it["u_hat"].fill_(-1)
+    for k, it in enumerate(items):
+        srv.submit(it, k)
+    done = {}
+    _drain(srv, done)
+    srv.close()
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        assert done[k][0] == lp.POLAR_OK
+        assert np.array_equal(bits_host(it["u_hat"], 1 << 16), refs[k]), k
     ctx.close()
