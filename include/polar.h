@@ -180,6 +180,28 @@ size_t polar_workspace_bytes(const polar_ctx* ctx, const polar_frame* frames, in
 int polar_sc_decode_batch(polar_ctx* ctx, const polar_frame* frames, int n_frames, void* stream);
 
 /*
+ * Allocation-free batch decoding, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same frames, options and results as polar_sc_decode_batch,
+ * but the workspace is the library's own static device buffer of
+ * POLAR_STATIC_SCRATCH_BYTES per device (held by each device the library
+ * runs on until the process ends; the context needs no workspace), and the
+ * call performs no device, pinned or host heap allocation: its host tables
+ * and pinned descriptor buffer are reserved by polar_ctx_create.
+ *   n_frames  0 .. POLAR_STATIC_MAX_FRAMES (POLAR_E_INVAL beyond)
+ * Frames above 2^cutover leaves need a slot of about 4N + N/8 bytes per
+ * workgroup in flight; the call runs as many workgroups as the buffer holds
+ * slots for (fewer than polar_sc_decode_batch for large frames) and returns
+ * POLAR_E_NOMEM if not even one fits.  Every call on a device shares that
+ * device's buffer, which keeps the last call's contents: calls that overlap
+ * on one device (two streams, two threads, two contexts) race, so the
+ * caller orders them (one stream, or events).
+ */
+#define POLAR_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+#define POLAR_STATIC_MAX_FRAMES 16384
+int polar_sc_decode_batch_static(polar_ctx* ctx, const polar_frame* frames, int n_frames, void* stream);
+
+/*
  * Plain per-frame GPU decoder, kept as the baseline the batched decoder is
  * measured against: one launch per frame, one workgroup, no pruning, frames
  * serially on the stream.  Same arguments, workspace and results.

@@ -38,7 +38,7 @@ COMMON = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["sc_device.hip", "polar_host.cpp", "polar_tune.cpp", "polar_serve.cpp",
+SOURCES = ["sc_device.hip", "polar_host.cpp", "polar_tune.cpp", "polar_serve.cpp", "polar_static.hip",
            "polar_fer.hip"] + sorted(
     os.path.relpath(f, CSRC) for f in glob.glob(os.path.join(CSRC, "variants", "*.hip")))
 

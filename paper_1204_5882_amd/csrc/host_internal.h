@@ -112,6 +112,13 @@ struct polar_ctx {
     mutable std::vector<int> occ_cache = std::vector<int>(5 * 2 * 2 * 2 * 26 * 8, 0);
     // autotuned launch configurations, key (f_kind, log2n of the largest frame)
     std::map<std::pair<int, int>, polar_host::LaunchCfg> tuned;
+    // allocation-free decoding (polar_sc_decode_batch_static): host tables
+    // reserved at creation, the device's static scratch buffer
+    polar_host::Stager static_stager;
+    polar_host::Plan static_plan;
+    std::vector<FrameDesc> static_descs;
+    void* static_scratch = nullptr;
+    size_t static_bytes = 0;
     // graph cache
     std::unordered_map<uint64_t, polar_host::GraphEntry> graphs;
     uint64_t graph_clock = 0;
@@ -146,5 +153,7 @@ int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* str
 // pointers); writes into out without reallocating when it has the capacity.
 void bind_descs(const Plan& p, void* ws, std::vector<FrameDesc>& out);
 int enqueue_launches(polar_ctx* c, const Plan& p, void* ws, hipStream_t s, bool plain, uint32_t* done);
+// Sets up the allocation-free path for a new context (its device current).
+int static_setup(polar_ctx* c);
 
 }  // namespace polar_host

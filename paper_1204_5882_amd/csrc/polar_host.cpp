@@ -610,6 +610,12 @@ extern "C" int polar_ctx_create(polar_ctx** out, int device, void* workspace, si
         c->n_cu = prop.multiProcessorCount;
     c->ws = workspace;
     c->ws_bytes = workspace ? ws_bytes : 0;
+    const int rc = static_setup(c);
+    if (rc) {
+        c->static_stager.release();
+        delete c;
+        return rc;
+    }
     *out = c;
     return ok();
 }
@@ -619,6 +625,7 @@ extern "C" int polar_ctx_destroy(polar_ctx* c) {
     {
         DeviceGuard g(c->device);
         c->stager.release();
+        c->static_stager.release();
         if (!c->graphs.empty()) (void)hipDeviceSynchronize();
         for (auto& kv : c->graphs) {
             (void)hipGraphExecDestroy(kv.second.exec);

@@ -36,13 +36,15 @@ POLAR_OPT_MAX_SLOTS = 4
 POLAR_OPT_TIMING = 5
 POLAR_OPT_GRAPH = 6
 POLAR_OPT_FWG = 7
+POLAR_STATIC_SCRATCH_BYTES = 256 << 20
+POLAR_STATIC_MAX_FRAMES = 16384
 
 # every symbol declared in include/polar.h
 EXPORTED = [
     "polar_last_error", "polar_version", "polar_build_frozen_set", "polar_encode",
     "polar_ctx_create", "polar_ctx_destroy", "polar_ctx_set_workspace", "polar_ctx_set_option",
     "polar_ctx_get_option", "polar_workspace_bytes", "polar_sc_decode_batch",
-    "polar_sc_decode_plain", "polar_autotune", "polar_query_launch", "polar_tune_clear",
+    "polar_sc_decode_plain", "polar_sc_decode_batch_static", "polar_autotune", "polar_query_launch", "polar_tune_clear",
     "polar_tune_save", "polar_tune_load", "polar_serve_open", "polar_serve_submit", "polar_serve_poll",
     "polar_serve_pending", "polar_serve_stats", "polar_serve_cancel", "polar_serve_close", "polar_serve",
     "polar_debug_lane_selftest", "polar_fer_generate_bsc", "polar_fer_workspace_bytes", "polar_fer_bsc",
@@ -137,6 +139,7 @@ def load():
         "polar_workspace_bytes": ([P, P, I], SZ),
         "polar_sc_decode_batch": ([P, P, I, P], I),
         "polar_sc_decode_plain": ([P, P, I, P], I),
+        "polar_sc_decode_batch_static": ([P, P, I, P], I),
         "polar_autotune": ([P, P, I, I, P, P, P, P, P, P, P, P], I),
         "polar_query_launch": ([P, I, I, I, P, P, P, P, P], I),
         "polar_tune_clear": ([P], I),
@@ -333,6 +336,11 @@ class Ctx:
                                        ctypes.addressof(res), _stream_handle(stream)))
         return ({"frames": res.frames, "frame_errors": res.frame_errors, "bit_errors": res.bit_errors},
                 bit_err[: int(n_frames)])
+
+    def decode_batch_static(self, frames: ctypes.Array, n: int, stream=None):
+        """polar_sc_decode_batch_static: the library's static device buffer as
+        workspace, no allocation (calls on one device must not overlap)."""
+        _check(self._lib.polar_sc_decode_batch_static(self._h, frames, int(n), _stream_handle(stream)))
 
     def decode_plain(self, frames: ctypes.Array, n: int, stream=None):
         _check(self._lib.polar_sc_decode_plain(self._h, frames, int(n), _stream_handle(stream)))
