@@ -15,6 +15,11 @@ Parity status of each function (what pins it is listed in the tests):
   frozen_set        pinned: as above plus tie-free boundary checks
   sc_decode minsum  pinned: naive per-bit SC (N <= 64), closed forms at scale
   sc_decode boxplus pinned: brute-force likelihood SC (N <= 16), mpmath f
+  phi_table         pinned: 60-digit mpmath phi, involution, monotonicity
+  sc_decode_fixed   pinned: naive per-bit SC in the same integer arithmetic
+                    (N <= 64), FP32 min-sum equality without saturation,
+                    saturation at the int16 bounds, phi-table LLRs within the
+                    quantization error of the exact FP64 update
 """
 from __future__ import annotations
 
@@ -67,6 +72,12 @@ def _load():
     lib.oracle_g_f32.restype = ctypes.c_float
     lib.oracle_f_boxplus.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.oracle_f_boxplus.restype = ctypes.c_double
+    lib.oracle_phi_table.argtypes = [ctypes.c_int, ctypes.c_int, P]
+    lib.oracle_phi_table.restype = ctypes.c_int
+    lib.oracle_sc_decode_fixed.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int]
+    lib.oracle_sc_decode_fixed.restype = ctypes.c_int
+    lib.oracle_f_fixed.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int]
+    lib.oracle_f_fixed.restype = ctypes.c_int32
     _lib = lib
     return lib
 
@@ -160,6 +171,58 @@ def sc_decode_batch(llr, frozen, fval, boxplus: bool = False, n_threads: int | N
     _load().oracle_sc_decode_batch(log2n, 1 if boxplus else 0, nfr, shared, _ptr(llr),
                                    _ptr(frozen), _ptr(fval), _ptr(u), int(n_threads))
     return u
+
+
+# Fixed point (Section 4): LLRs as integers in units of 2^-FIXED_FRAC,
+# saturated to +-FIXED_MAX; the phi table has FIXED_TABLE_LEN entries.
+FIXED_FRAC = 4
+FIXED_MAX = 32767
+FIXED_TABLE_LEN = 256
+FIXED_MINSUM, FIXED_PHI = 0, 1
+
+
+def phi_table(frac: int = FIXED_FRAC, length: int = FIXED_TABLE_LEN) -> np.ndarray:
+    """T[i] = round(phi(i 2^-frac) 2^frac), phi(x) = -ln tanh(x/2) (Section 4's
+    table), T[0] = FIXED_MAX."""
+    out = np.empty(length, np.int32)
+    if _load().oracle_phi_table(int(frac), int(length), _ptr(out)) != 0:
+        raise ValueError("oracle_phi_table failed")
+    return out
+
+
+def quantize(llr, frac: int = FIXED_FRAC) -> np.ndarray:
+    """Channel LLRs to fixed point: round(L 2^frac) (half away from zero),
+    saturated to +-FIXED_MAX."""
+    q = np.round(np.asarray(llr, np.float64) * (1 << frac))
+    return np.clip(q, -FIXED_MAX, FIXED_MAX).astype(np.int32)
+
+
+def sc_decode_fixed(llr_q, frozen, fval, kind: int = FIXED_MINSUM, teacher=None, want_leaf: bool = False,
+                    table=None):
+    """Fixed-point SC (Section 4): kind FIXED_MINSUM (saturating min-sum) or
+    FIXED_PHI (phi-table exact update).  llr_q: N integers.  Returns (u_hat,
+    leaf LLRs int32 or None)."""
+    llr = np.ascontiguousarray(np.asarray(llr_q, dtype=np.int32))
+    n = llr.shape[0]
+    log2n = n.bit_length() - 1
+    if (1 << log2n) != n:
+        raise ValueError("N must be a power of two")
+    frozen = _bits(frozen, n)
+    fval = _bits(fval, n)
+    t = _bits(teacher, n) if teacher is not None else None
+    tab = np.ascontiguousarray(table if table is not None else phi_table(), np.int32)
+    u = np.empty(n, np.uint8)
+    leaf = np.empty(n, np.int32) if want_leaf else None
+    rc = _load().oracle_sc_decode_fixed(log2n, int(kind), _ptr(llr), _ptr(frozen), _ptr(fval), _ptr(t),
+                                        _ptr(u), _ptr(leaf), _ptr(tab), int(tab.size))
+    if rc != 0:
+        raise ValueError("oracle_sc_decode_fixed failed")
+    return u, leaf
+
+
+def f_fixed(kind: int, a: int, b: int, table=None) -> int:
+    tab = np.ascontiguousarray(table if table is not None else phi_table(), np.int32)
+    return int(_load().oracle_f_fixed(int(kind), int(a), int(b), _ptr(tab), int(tab.size)))
 
 
 def f_minsum(a: float, b: float) -> float:

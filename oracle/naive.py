@@ -120,3 +120,52 @@ def brute_sc(llr, frozen, fval, teacher=None):
         u.append(ui)
         used.append(int(teacher[i]) if teacher is not None else ui)
     return np.array(u, np.uint8), np.array(leaves, np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Fixed point (Section 4: fixed-point LLRs, phi-table check update), per bit.
+# Integers in units of 2^-frac, saturated to +-32767.
+# ---------------------------------------------------------------------------
+FIXED_MAX = 32767
+
+
+def _sat(x: int) -> int:
+    return max(-FIXED_MAX, min(FIXED_MAX, x))
+
+
+def f_fixed(a: int, b: int, kind: int, table) -> int:
+    mag = min(abs(a), abs(b))
+    if kind == 1:
+        n = len(table)
+        phi = lambda x: int(table[x]) if x < n else 0  # noqa: E731
+        mag = min(mag, phi(min(phi(abs(a)) + phi(abs(b)), n - 1)))
+    return -mag if (a < 0) != (b < 0) else mag
+
+
+def _leaf_fixed(alpha, i, decided, kind, table):
+    m = len(alpha)
+    if m == 1:
+        return alpha[0]
+    h = m // 2
+    if i < h:
+        return _leaf_fixed([f_fixed(alpha[j], alpha[j + h], kind, table) for j in range(h)], i, decided, kind, table)
+    beta = encode_matrix(decided[:h])
+    return _leaf_fixed([_sat(alpha[j + h] - alpha[j] if beta[j] else alpha[j + h] + alpha[j]) for j in range(h)],
+                       i - h, decided[h:], kind, table)
+
+
+def naive_sc_fixed(llr_q, frozen, fval, kind, table, teacher=None):
+    """Per-bit fixed-point SC (partial sums by explicit re-encoding).
+    Returns (u_hat, leaf LLRs as integers)."""
+    llr = [int(v) for v in np.asarray(llr_q)]
+    n = len(llr)
+    if n > 64:
+        raise ValueError("naive_sc_fixed is for N <= 64")
+    u, used, leaves = [], [], []
+    for i in range(n):
+        li = _leaf_fixed(llr, i, used, kind, table)
+        leaves.append(li)
+        ui = int(fval[i]) if frozen[i] else int(li < 0)
+        u.append(ui)
+        used.append(int(teacher[i]) if teacher is not None else ui)
+    return np.array(u, np.uint8), np.array(leaves, np.int64)

@@ -312,10 +312,151 @@ int oracle_sc_decode(int log2n, int boxplus, const float* llr, const uint8_t* fr
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Fixed-point SC (Section 4: the decoder keeps LLRs in fixed point, and its */
+/* check update uses phi(x) = -ln tanh(x/2) from a table, the paper's main   */
+/* optimization; phi is its own inverse, so the exact update is             */
+/* f = sign(a) sign(b) phi(phi(|a|) + phi(|b|))).                           */
+/*                                                                          */
+/* LLRs are integers in units of 2^-FRAC (FRAC = 4 here), saturated to      */
+/* +-32767 (int16 range).  Two check updates:                               */
+/*   kind 0, saturating min-sum: f = sign(a) sign(b) min(|a|, |b|)           */
+/*   kind 1, phi table:          f = sign(a) sign(b) min(T[min(T[|a|] +     */
+/*       T[|b|], len-1)], |a|, |b|), T[i] = phi(i 2^-FRAC) in the same units */
+/*       (T[i] = 0 beyond the table), the min with |a|, |b| because the     */
+/*       exact update never exceeds either magnitude (it also stands in for  */
+/*       T[0] = phi(0) = infinity)                                           */
+/* Variable update for both: g = sat(b + (1 - 2u) a).  Decisions [L < 0].    */
+/* ------------------------------------------------------------------------ */
+#define FIXED_MAX 32767
+
+static int32_t sat16(int32_t x) { return x > FIXED_MAX ? FIXED_MAX : (x < -FIXED_MAX ? -FIXED_MAX : x); }
+
+/* T[i] = round(phi(i 2^-frac) 2^frac), phi(x) = ln(1 + 2 / expm1(x)) (the
+ * same function as -ln tanh(x/2), without cancellation for large x),
+ * rounded half up, capped at FIXED_MAX; T[0] = FIXED_MAX. */
+int oracle_phi_table(int frac, int len, int32_t* out) {
+    if (frac < 0 || frac > 12 || len < 2 || !out) return -1;
+    const double step = ldexp(1.0, -frac);
+    out[0] = FIXED_MAX;
+    for (int i = 1; i < len; ++i) {
+        double v = log1p(2.0 / expm1(i * step)) / step;
+        double r = floor(v + 0.5);
+        out[i] = r > FIXED_MAX ? FIXED_MAX : (int32_t)r;
+    }
+    return 0;
+}
+
+typedef struct {
+    const uint8_t* frozen;
+    const uint8_t* fval;
+    const uint8_t* teacher;
+    uint8_t* u_hat;
+    int32_t* leaf;
+    int kind;
+    const int32_t* table;
+    int len;
+    int32_t** alpha_lvl;
+    uint8_t** bl_lvl;
+    uint8_t** br_lvl;
+} fx_ctx;
+
+static int32_t fx_phi(const fx_ctx* c, int32_t x) { return x < c->len ? c->table[x] : 0; }
+
+static int32_t fx_f(const fx_ctx* c, int32_t a, int32_t b) {
+    int32_t A = a < 0 ? -a : a, B = b < 0 ? -b : b;
+    int32_t m = A < B ? A : B;
+    int32_t r = m;
+    if (c->kind == 1) {
+        int32_t s = fx_phi(c, A) + fx_phi(c, B);
+        int32_t t = fx_phi(c, s < c->len ? s : c->len - 1);
+        r = t < m ? t : m;
+    }
+    return ((a < 0) != (b < 0)) ? -r : r;
+}
+
+static int32_t fx_g(int32_t a, int32_t b, int u) { return sat16(u ? b - a : b + a); }
+
+static void dec_fixed(const int32_t* alpha, int64_t m, int64_t off, int depth, fx_ctx* c, uint8_t* beta) {
+    if (m == 1) {
+        int32_t L = alpha[0];
+        if (c->leaf) c->leaf[off] = L;
+        int u = c->frozen[off] ? c->fval[off] : (L < 0);
+        c->u_hat[off] = (uint8_t)u;
+        beta[0] = c->teacher ? c->teacher[off] : (uint8_t)u;
+        return;
+    }
+    int64_t h = m / 2;
+    int32_t* a = c->alpha_lvl[depth];
+    uint8_t* bl = c->bl_lvl[depth];
+    uint8_t* br = c->br_lvl[depth];
+    for (int64_t j = 0; j < h; ++j) a[j] = fx_f(c, alpha[j], alpha[j + h]);
+    dec_fixed(a, h, off, depth + 1, c, bl);
+    for (int64_t j = 0; j < h; ++j) a[j] = fx_g(alpha[j], alpha[j + h], bl[j]);
+    dec_fixed(a, h, off + h, depth + 1, c, br);
+    for (int64_t j = 0; j < h; ++j) {
+        beta[j] = (uint8_t)(bl[j] ^ br[j]);
+        beta[j + h] = br[j];
+    }
+}
+
+/* Decode one frame in fixed point.  llr: N integers (channel LLRs in units
+ * of 2^-frac, inside +-32767); kind 0 saturating min-sum, 1 phi table
+ * (table of len entries, from oracle_phi_table); leaf (nullable) receives
+ * the N decision LLRs.  Returns 0 or -1. */
+int oracle_sc_decode_fixed(int log2n, int kind, const int32_t* llr, const uint8_t* frozen, const uint8_t* fval,
+                           const uint8_t* teacher, uint8_t* u_hat, int32_t* leaf, const int32_t* table,
+                           int len) {
+    if (log2n < 0 || log2n > 30 || !llr || !frozen || !fval || !u_hat) return -1;
+    if (kind != 0 && kind != 1) return -1;
+    if (kind == 1 && (!table || len < 2)) return -1;
+    int64_t n = (int64_t)1 << log2n;
+    for (int64_t j = 0; j < n; ++j)
+        if (llr[j] > FIXED_MAX || llr[j] < -FIXED_MAX) return -1;
+    fx_ctx c;
+    c.frozen = frozen;
+    c.fval = fval;
+    c.teacher = teacher;
+    c.u_hat = u_hat;
+    c.leaf = leaf;
+    c.kind = kind;
+    c.table = table;
+    c.len = len;
+    c.alpha_lvl = (int32_t**)calloc((size_t)log2n + 1, sizeof(int32_t*));
+    c.bl_lvl = (uint8_t**)calloc((size_t)log2n + 1, sizeof(uint8_t*));
+    c.br_lvl = (uint8_t**)calloc((size_t)log2n + 1, sizeof(uint8_t*));
+    for (int d = 0; d < log2n; ++d) {
+        int64_t h = n >> (d + 1);
+        c.alpha_lvl[d] = (int32_t*)malloc(sizeof(int32_t) * (size_t)h);
+        c.bl_lvl[d] = (uint8_t*)malloc((size_t)h);
+        c.br_lvl[d] = (uint8_t*)malloc((size_t)h);
+    }
+    uint8_t* beta = (uint8_t*)malloc((size_t)n);
+    dec_fixed(llr, n, 0, 0, &c, beta);
+    free(beta);
+    for (int d = 0; d < log2n; ++d) {
+        free(c.alpha_lvl[d]);
+        free(c.bl_lvl[d]);
+        free(c.br_lvl[d]);
+    }
+    free(c.alpha_lvl);
+    free(c.bl_lvl);
+    free(c.br_lvl);
+    return 0;
+}
+
 /* Scalar updates exported for the tests that pin them. */
 float oracle_f_minsum(float a, float b) { return f_minsum(a, b); }
 float oracle_g_f32(float a, float b, int u) { return g_f32(a, b, u); }
 double oracle_f_boxplus(double a, double b) { return f_boxplus(a, b); }
+int32_t oracle_f_fixed(int kind, int32_t a, int32_t b, const int32_t* table, int len) {
+    fx_ctx c;
+    memset(&c, 0, sizeof c);
+    c.kind = kind;
+    c.table = table;
+    c.len = len;
+    return fx_f(&c, a, b);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Many frames, one frame per thread (the CPU baseline).                    */

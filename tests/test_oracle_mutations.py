@@ -27,6 +27,12 @@ MUTATIONS = {
     "bhatt_children_swapped": ("bz[2 * j] = mz;", "bz[2 * j] = pz;"),
     "boxplus_log_sign": ("return s * (m + log1p(exp(-(A + B))) - log1p(exp(-fabs(A - B))));",
                          "return s * (m - log1p(exp(-(A + B))) - log1p(exp(-fabs(A - B))));"),
+    "fixed_g_unsaturated": ("static int32_t fx_g(int32_t a, int32_t b, int u) { return sat16(u ? b - a : b + a); }",
+                            "static int32_t fx_g(int32_t a, int32_t b, int u) { return u ? b - a : b + a; }"),
+    "fixed_phi_sum_drops_term": ("int32_t s = fx_phi(c, A) + fx_phi(c, B);", "int32_t s = fx_phi(c, A);"),
+    "fixed_phi_drops_min_clamp": ("r = t < m ? t : m;", "r = t;"),
+    "phi_table_shifted": ("double v = log1p(2.0 / expm1(i * step)) / step;",
+                          "double v = log1p(2.0 / expm1((i + 1) * step)) / step;"),
 }
 
 
@@ -44,6 +50,8 @@ def _build_mutant(tmp_path, name):
     lib.oracle_sc_decode.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P]
     lib.oracle_encode.argtypes = [ctypes.c_int, P, P]
     lib.oracle_bhattacharyya.argtypes = [ctypes.c_int, ctypes.c_double, P, P]
+    lib.oracle_sc_decode_fixed.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int]
+    lib.oracle_phi_table.argtypes = [ctypes.c_int, ctypes.c_int, P]
     return lib
 
 
@@ -105,6 +113,44 @@ def _bhatt_pin_catches(lib):
     return not np.allclose(np.exp(lz), [0.9375, 0.5625, 0.4375, 0.0625])
 
 
+def _fixed_pin_catches(lib):
+    """The fixed-point decoder against the per-bit naive decoder in the same
+    integer arithmetic (saturation exercised), both check updates."""
+    g = np.random.default_rng(12)
+    table = oracle.phi_table()
+    tab = np.ascontiguousarray(table, np.int32)
+    for kind in (0, 1):
+        for log2n in (2, 4, 5):
+            n = 1 << log2n
+            for trial in range(6):
+                llr = (g.integers(-32767, 32768, n) if trial % 2 else g.integers(-90, 91, n)).astype(np.int32)
+                mask = (g.random(n) < 0.4).astype(np.uint8)
+                fval = (g.integers(0, 2, n) & mask).astype(np.uint8)
+                u = np.empty(n, np.uint8)
+                leaf = np.empty(n, np.int32)
+                lib.oracle_sc_decode_fixed(log2n, kind, _p(llr), _p(mask), _p(fval), None, _p(u), _p(leaf),
+                                           _p(tab), int(tab.size))
+                un, ln = naive.naive_sc_fixed(llr, mask, fval, kind, table)
+                if not (np.array_equal(u, un) and np.array_equal(leaf, ln)):
+                    return True
+    return False
+
+
+def _phi_table_pin_catches(lib):
+    """The table against phi = -ln tanh(x/2) at 60 digits."""
+    import mpmath
+
+    mpmath.mp.dps = 60
+    out = np.empty(oracle.FIXED_TABLE_LEN, np.int32)
+    lib.oracle_phi_table(oracle.FIXED_FRAC, oracle.FIXED_TABLE_LEN, _p(out))
+    step = mpmath.mpf(1) / (1 << oracle.FIXED_FRAC)
+    for i in range(1, out.size):
+        v = -mpmath.log(mpmath.tanh(i * step / 2)) / step
+        if out[i] != min(oracle.FIXED_MAX, int(mpmath.floor(v + mpmath.mpf("0.5")))):
+            return True
+    return False
+
+
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_planted_mistake_is_caught(tmp_path, name):
     lib = _build_mutant(tmp_path, name)
@@ -112,6 +158,10 @@ def test_planted_mistake_is_caught(tmp_path, name):
         "encode_drops_xor": _encode_pin_catches,
         "bhatt_children_swapped": _bhatt_pin_catches,
         "boxplus_log_sign": _boxplus_pin_catches,
+        "fixed_g_unsaturated": _fixed_pin_catches,
+        "fixed_phi_sum_drops_term": _fixed_pin_catches,
+        "fixed_phi_drops_min_clamp": _fixed_pin_catches,
+        "phi_table_shifted": _phi_table_pin_catches,
     }.get(name, _minsum_pin_catches)(lib)
     assert caught, f"mutation {name} was not detected by its pin"
 
@@ -127,6 +177,10 @@ def test_unmutated_source_passes_the_same_pins(tmp_path):
     lib.oracle_sc_decode.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P]
     lib.oracle_encode.argtypes = [ctypes.c_int, P, P]
     lib.oracle_bhattacharyya.argtypes = [ctypes.c_int, ctypes.c_double, P, P]
+    lib.oracle_sc_decode_fixed.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int]
+    lib.oracle_phi_table.argtypes = [ctypes.c_int, ctypes.c_int, P]
+    assert not _fixed_pin_catches(lib)
+    assert not _phi_table_pin_catches(lib)
     assert not _minsum_pin_catches(lib)
     assert not _boxplus_pin_catches(lib)
     assert not _encode_pin_catches(lib)
