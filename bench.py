@@ -125,6 +125,14 @@ def mixed_frames(seed=4):
     return [out[i] for i in perm]
 
 
+# the headline frames in the paper's fixed-point arithmetic (Section 4):
+# channel LLRs in units of 2^-4, saturating min-sum or the phi table
+CONFIGS["n20-bsc-x256-q16"] = dict(desc="N=2^20, BSC p=0.03, rate 0.75, 256 frames, fixed-point LLRs (2^-4), "
+                                   "saturating min-sum", frames=[(20, "bsc", 0.03, 262144)] * 256, fkind=2,
+                                   seed_base=2000, fixed=True)
+CONFIGS["n20-bsc-x256-phi"] = dict(desc="N=2^20, BSC p=0.03, rate 0.75, 256 frames, fixed-point LLRs (2^-4), "
+                                   "phi-table check update", frames=[(20, "bsc", 0.03, 262144)] * 256, fkind=3,
+                                   seed_base=2000, fixed=True)
 CONFIGS["mixed-n16-22-x512"] = dict(desc="512 frames, N=2^16..2^22 uniform in log2 N, half BSC p~U[0.01,0.05], half BIAWGN "
                             "sigma~U[0.8,1.2], union-bound rates (FER bound 0.1), FP32 min-sum",
                        frames=None, fkind=0, seed_base=40000)
@@ -160,6 +168,8 @@ def make_inputs(cfg_name, lp, torch, dev):
             return synth.unpack_bits(x.cpu().numpy().view(np.uint32), n)
 
         u, fval, llr = synth.frame(cfg["seed_base"] + k, log2n, ch, prm, mbits, gpu_encode)
+        if cfg.get("fixed"):
+            llr = synth.fixed_point(llr)
         items.append(dict(log2n=log2n, f_kind=cfg["fkind"], llr=torch.from_numpy(llr).to(dev),
                           frozen_mask=mdev,
                           frozen_vals=torch.from_numpy(synth.pack_bits(fval).view(np.int32).copy()).to(dev),
@@ -222,6 +232,8 @@ def oracle_frames(cfg_name, count):
             masks[key] = oracle.frozen_set(log2n, z0_of(ch, prm), nf, 0.1)[0]
         mask = masks[key]
         _, fval, llr = synth.frame(cfg["seed_base"] + k, log2n, ch, prm, mask, lambda v, n=log2n: oracle.encode(n, v))
+        if cfg.get("fixed"):
+            llr = oracle.quantize(llr).astype(np.float32)
         out.append((llr, mask, fval))
     return out
 
@@ -230,13 +242,24 @@ def cpu_baseline(cfg_name, host, boxplus, budget_s=20.0):
     """The oracle as it is, on a bounded sample of the same frames (about
     budget_s of CPU work), one frame per host thread.  Returns the baseline,
     the oracle's u-hat of the sample, and whether the oracle-built inputs
-    equal the ones the GPU decoded."""
+    equal the ones the GPU decoded.  Fixed-point workloads run the oracle's
+    integer decoder (saturating min-sum or phi table)."""
+    import concurrent.futures as cf
+
     import oracle
+
+    cfg = CONFIGS[cfg_name]
+    fixed_kind = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI}.get(cfg["fkind"])
+
+    def one_frame(h):
+        if fixed_kind is not None:
+            return oracle.sc_decode_fixed(h[0].astype(np.int32), h[1], h[2], fixed_kind)[0]
+        return oracle.sc_decode(h[0], h[1], h[2], boxplus=boxplus)[0]
 
     threads = host_threads()
     first = oracle_frames(cfg_name, 1)
     t0 = time.perf_counter()
-    oracle.sc_decode(first[0][0], first[0][1], first[0][2], boxplus=boxplus)
+    one_frame(first[0])
     one = max(time.perf_counter() - t0, 1e-4)
     count = max(1, min(len(host), int(budget_s / one)))
     sample = oracle_frames(cfg_name, count)
@@ -245,15 +268,15 @@ def cpu_baseline(cfg_name, host, boxplus, budget_s=20.0):
     n = sample[0][0].size
     same = all(h[0].size == n for h in sample)
     t0 = time.perf_counter()
-    if same:
+    if same and fixed_kind is None:
         llr = np.stack([h[0] for h in sample])
         masks = np.stack([h[1] for h in sample])
         fval = np.stack([h[2] for h in sample])
         u = oracle.sc_decode_batch(llr, masks, fval, boxplus=boxplus, n_threads=threads)
         outs = [u[k] for k in range(count)]
-    else:
-        outs = [oracle.sc_decode(h[0], h[1], h[2], boxplus=boxplus)[0] for h in sample]
-        threads = 1
+    else:  # one frame per host thread (the oracle's C code runs without the interpreter lock)
+        with cf.ThreadPoolExecutor(threads) as ex:
+            outs = list(ex.map(one_frame, sample))
     wall = time.perf_counter() - t0
     bits = sum(h[0].size for h in sample)
     return dict(value=round(bits / wall / 1e6, 2), unit="Mbit/s", cores=threads, kind="oracle",
@@ -448,6 +471,8 @@ def main(argv=None):
     ap.add_argument("--prune", type=int, default=1)
     ap.add_argument("--waves", type=int, default=0, help="wavefronts per workgroup (0 = library default)")
     ap.add_argument("--cutover", type=int, default=0, help="register-resident subtree log2 (0 = library default)")
+    ap.add_argument("--fwg", type=int, default=0,
+                    help="frames per workgroup for frames of at most 2^cutover leaves (0 = library default)")
     ap.add_argument("--graph", type=int, default=0, help="replay the batch through a HIP graph")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -495,6 +520,8 @@ def main(argv=None):
         ctx.set_option(lp.POLAR_OPT_WG_WAVES, args.waves)
     if args.cutover:
         ctx.set_option(lp.POLAR_OPT_CUTOVER, args.cutover)
+    if args.fwg:
+        ctx.set_option(lp.POLAR_OPT_FWG, args.fwg)
     if args.graph:
         ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
     frames = lp.make_frames(items)
@@ -517,6 +544,7 @@ def main(argv=None):
     achieved = alg_bytes / (ev_ms / 1e3) / 1e9
     source = decoder_source_hash()
     tr = measured_traffic(args.config, source) if (cfg["fkind"] == 0 and args.prune and not args.cutover) else None
+    dtype = {0: "f32", 1: "f32", 2: "q16 (fixed point, f32 registers)", 3: "q16 (fixed point, f32 registers)"}
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None if tr is None else int(tr["bytes"]))
     if tr is not None:
@@ -525,10 +553,11 @@ def main(argv=None):
     # correctness spot check of the timed output against the oracle (CPU leg)
     out = dict(metric=METRIC, value=round(value, 1), unit="Mbit/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="f32", data="synthetic",
+               vs_baseline=None, dtype=dtype[cfg["fkind"]], data="synthetic",
                config=dict(workload=f"{args.config}: {cfg['desc']}", frames=n,
                            bits_per_step=total_bits, info_bits_per_step=info_bits,
-                           f_kind="boxplus" if cfg["fkind"] else "minsum", prune=bool(args.prune),
+                           f_kind=["minsum", "boxplus", "minsum_q16", "phi_q16"][cfg["fkind"]],
+                           prune=bool(args.prune),
                            graph=bool(args.graph), decoder_source=source,
                            launch=ctx.query_launch(cfg["fkind"], max(it["log2n"] for it in items), n),
                            tuned=tuned),
@@ -596,7 +625,7 @@ def main(argv=None):
 
     if not args.no_cpu:
         print("[bench] CPU oracle leg", file=sys.stderr, flush=True)
-        cb, outs, same_inputs, sample = cpu_baseline(args.config, host, boxplus=bool(cfg["fkind"]))
+        cb, outs, same_inputs, sample = cpu_baseline(args.config, host, boxplus=cfg["fkind"] == 1)
         out["cpu_baseline"] = cb
         out["oracle_inputs_equal_gpu_inputs"] = same_inputs
         # the batched GPU output of the timed run, checked on the same sample:
@@ -608,7 +637,7 @@ def main(argv=None):
         tolerated = 0
         for k, ref in enumerate(outs):
             got = synth.unpack_bits(items[k]["u_hat"].cpu().numpy().view(np.uint32), items[k]["llr"].numel())
-            if not cfg["fkind"]:
+            if cfg["fkind"] != 1:
                 ok &= bool(np.array_equal(got, ref))
             else:
                 import oracle
@@ -620,7 +649,7 @@ def main(argv=None):
                 ok &= bool(np.array_equal(got[fz], fval[fz])) and bool(np.all(np.abs(l_ref[dis]) < 1e-6))
                 tolerated += int(dis.sum())
         out["oracle_agrees_on_sample"] = ok
-        out["oracle_check"] = dict(frames=len(outs), rule="bit-exact" if not cfg["fkind"] else
+        out["oracle_check"] = dict(frames=len(outs), rule="bit-exact" if cfg["fkind"] != 1 else
                                    "teacher-forced FP64 oracle, |L_ref| < 1e-6 at differing decisions",
                                    tolerated_differences=tolerated)
     out["paper_context"] = dict(value=9.5, unit="Mbit/s", note="SC decoding, BSC 2%, N=2^20, one core of an "

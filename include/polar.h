@@ -48,6 +48,17 @@ extern "C" {
 /* Check-node update used by SC decoding (Section 4). */
 #define POLAR_F_MINSUM 0  /* sign(a) sign(b) min(|a|,|b|), FP32, bit-exact        */
 #define POLAR_F_BOXPLUS 1 /* 2 atanh(tanh(a/2) tanh(b/2)) (the phi-function form), FP32 */
+/* Fixed point (Section 4: fixed-point LLRs, check update from a phi table).
+   The frame's llr array holds integers in units of 2^-POLAR_FIXED_FRAC with
+   |L| <= POLAR_FIXED_MAX, stored as float (exact); every variable update
+   g = b +- a saturates to +-POLAR_FIXED_MAX; leaf LLRs come out in the same
+   units.  Results are bit-exact against integer arithmetic. */
+#define POLAR_F_MINSUM_Q16 2 /* saturating min-sum                               */
+#define POLAR_F_PHI_Q16 3    /* sign(a) sign(b) min(T[min(T[|a|] + T[|b|], 255)], |a|, |b|),
+                                T[i] = round(phi(i 2^-4) 2^4), phi(x) = -ln tanh(x/2),
+                                T[0] = 32767; T is 0 from index 67 on            */
+#define POLAR_FIXED_FRAC 4
+#define POLAR_FIXED_MAX 32767
 
 #define POLAR_MAX_LOG2N 24
 
@@ -99,8 +110,9 @@ int polar_encode(int log2n, int n_frames, const uint32_t* u, uint32_t* x, void* 
    aligned, the other buffers 4-byte aligned. */
 typedef struct polar_frame {
     int32_t log2n;                /* 1 .. POLAR_MAX_LOG2N                              */
-    int32_t f_kind;               /* POLAR_F_MINSUM or POLAR_F_BOXPLUS                  */
-    const float* llr;             /* N channel LLRs, 16-byte aligned                     */
+    int32_t f_kind;               /* POLAR_F_MINSUM, _BOXPLUS, _MINSUM_Q16 or _PHI_Q16  */
+    const float* llr;             /* N channel LLRs, 16-byte aligned (fixed-point
+                                     kinds: integers in units of 2^-4, see above)    */
     const uint32_t* frozen_mask;  /* max(1, N/32) words, 1 = frozen; may be shared      */
     const uint32_t* frozen_vals;  /* max(1, N/32) words, revealed values of u_F;
                                      bits outside the mask are ignored                 */
@@ -324,6 +336,8 @@ int polar_serve(polar_ctx* ctx, const polar_serve_cfg* cfg, polar_next_fn next, 
  *   channel error, bit i = Philox((i >> 2, 1, 0, 0), key)[i & 3] < floor(p 2^32)
  *   x = u G_N; L_i = +L0 where x_i equals the error bit, else -L0, with
  *   L0 = ln((1 - p) / p) computed in double and rounded once to float32
+ *   (fixed_point != 0, and the fixed-point f_kinds of polar_fer_bsc: L0 in
+ *   units of 2^-POLAR_FIXED_FRAC, rounded half to even)
  *   frozen values = u on the frozen set
  * A frame is in error when its u-hat differs from u in any position.
  *
@@ -338,7 +352,7 @@ int polar_serve(polar_ctx* ctx, const polar_serve_cfg* cfg, polar_next_fn next, 
  */
 typedef struct polar_fer_cfg {
     int32_t log2n;                /* 1 .. POLAR_MAX_LOG2N                              */
-    int32_t f_kind;               /* POLAR_F_MINSUM or POLAR_F_BOXPLUS                  */
+    int32_t f_kind;               /* any POLAR_F_* check update                        */
     double p;                     /* BSC crossover probability, 0 < p < 1/2            */
     const uint32_t* frozen_mask;  /* device, max(1, N/32) words, 1 = frozen            */
     uint64_t seed;                /* low 32 bits used                                  */
@@ -354,9 +368,9 @@ typedef struct polar_fer_result {
     int64_t bit_errors;
 } polar_fer_result;
 
-int polar_fer_generate_bsc(int log2n, double p, const uint32_t* frozen_mask, uint64_t seed, int64_t frame0,
-                           int n_frames, uint32_t* u, uint32_t* frozen_vals, uint32_t* x_scratch, float* llr,
-                           void* stream);
+int polar_fer_generate_bsc(int log2n, double p, int fixed_point, const uint32_t* frozen_mask, uint64_t seed,
+                           int64_t frame0, int n_frames, uint32_t* u, uint32_t* frozen_vals,
+                           uint32_t* x_scratch, float* llr, void* stream);
 /* Returns 0 on invalid arguments. */
 size_t polar_fer_workspace_bytes(const polar_ctx* ctx, const polar_fer_cfg* cfg);
 int polar_fer_bsc(polar_ctx* ctx, const polar_fer_cfg* cfg, void* workspace, size_t ws_bytes,
@@ -368,6 +382,11 @@ int polar_fer_bsc(polar_ctx* ctx, const polar_fer_cfg* cfg, void* workspace, siz
  * decoder is built from.  out: device, 1024 words.
  */
 int polar_debug_lane_selftest(uint32_t* out, void* stream);
+
+/* Diagnostics: the 256-entry phi table T of POLAR_F_PHI_Q16 as the decoder
+   builds it on the device (FP64 on the GPU), as floats.  out: device, 256
+   floats. */
+int polar_debug_phi_table(float* out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -191,7 +191,7 @@ def phi_table(frac: int = FIXED_FRAC, length: int = FIXED_TABLE_LEN) -> np.ndarr
 
 
 def quantize(llr, frac: int = FIXED_FRAC) -> np.ndarray:
-    """Channel LLRs to fixed point: round(L 2^frac) (half away from zero),
+    """Channel LLRs to fixed point: round(L 2^frac) (round half to even),
     saturated to +-FIXED_MAX."""
     q = np.round(np.asarray(llr, np.float64) * (1 << frac))
     return np.clip(q, -FIXED_MAX, FIXED_MAX).astype(np.int32)

@@ -21,6 +21,7 @@ Frame f of a run with seed s, key = (s mod 2^32, f):
   channel error at bit i (BSC(p))    = Philox((i >> 2, 1, 0, 0), key)[i & 3] < T,
                                        T = floor(p 2^32)
   x = u G_N, y = x xor e, L_i = (1 - 2 y_i) L0, L0 = float32(ln((1 - p) / p))
+  (for the fixed-point decoders L0 in units of 2^-4, rounded half to even)
   frozen values = u on the frozen set
 (for N < 32 the low N bits of word 0).  A frame is in error when u-hat != u.
 """
@@ -83,8 +84,9 @@ def bsc_l0(p: float) -> np.float32:
     return np.float32(math.log((1.0 - p) / p))
 
 
-def bsc_frame(seed: int, frame: int, log2n: int, p: float, mask: np.ndarray):
-    """(u bits, frozen values, LLRs float32, channel error bits) of frame f."""
+def bsc_frame(seed: int, frame: int, log2n: int, p: float, mask: np.ndarray, fixed_point: bool = False):
+    """(u bits, frozen values, LLRs float32, channel error bits) of frame f;
+    fixed_point: LLRs in units of 2^-4 (the fixed-point decoders' input)."""
     n = 1 << log2n
     key = (seed & MASK32, frame & MASK32)
     words = _stream(0, max(1, n // 32), key)
@@ -92,7 +94,7 @@ def bsc_frame(seed: int, frame: int, log2n: int, p: float, mask: np.ndarray):
     e = (_stream(1, n, key) < np.uint32(bsc_threshold(p))).astype(np.uint8)
     x = oracle.encode(log2n, u)
     y = x ^ e
-    l0 = bsc_l0(p)
+    l0 = bsc_l0(p) if not fixed_point else np.float32(oracle.quantize([math.log((1.0 - p) / p)])[0])
     llr = np.where(y == 1, -l0, l0).astype(np.float32)
     fval = (u & mask).astype(np.uint8)
     return u, fval, llr, e
@@ -106,16 +108,20 @@ def bsc_capacity(p: float) -> float:
 
 
 def fer_bsc(seed: int, frame0: int, n_frames: int, log2n: int, p: float, mask: np.ndarray,
-            boxplus: bool = False, n_threads: int | None = None):
+            boxplus: bool = False, n_threads: int | None = None, fixed_kind: int | None = None):
     """Monte-Carlo FER of SC decoding on BSC(p): returns (frames in error,
     bit errors, per-frame error flags).  Frames are decoded by the oracle's
-    SC decoder (FP32 min-sum, or FP64 box-plus), one per host thread."""
+    SC decoder (FP32 min-sum, FP64 box-plus, or with fixed_kind the
+    fixed-point decoder on fixed-point frames), one per host thread."""
     import concurrent.futures as cf
     import os
 
     def one(f):
-        u, fval, llr, _ = bsc_frame(seed, frame0 + f, log2n, p, mask)
-        uh = oracle.sc_decode(llr, mask, fval, boxplus=boxplus)[0]
+        u, fval, llr, _ = bsc_frame(seed, frame0 + f, log2n, p, mask, fixed_point=fixed_kind is not None)
+        if fixed_kind is not None:
+            uh = oracle.sc_decode_fixed(llr.astype(np.int32), mask, fval, fixed_kind)[0]
+        else:
+            uh = oracle.sc_decode(llr, mask, fval, boxplus=boxplus)[0]
         return int((uh != u).sum())
 
     n_threads = n_threads or max(1, min(16, len(os.sched_getaffinity(0))))

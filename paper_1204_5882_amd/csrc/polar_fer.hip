@@ -12,6 +12,7 @@
 //   u word w            = Philox((w >> 2, 0, 0, 0), key)[w & 3]
 //   channel error, bit i = Philox((i >> 2, 1, 0, 0), key)[i & 3] < floor(p 2^32)
 //   x = u G_N, L_i = +L0 if x_i = e_i else -L0, L0 = float32(ln((1 - p)/p))
+//   (fixed-point check updates: L0 in units of 2^-4, rounded half to even)
 //   frozen values = u on the frozen set
 // A frame is in error when its u-hat differs from u anywhere.
 #include <hip/hip_runtime.h>
@@ -164,7 +165,7 @@ int check_cfg(const polar_fer_cfg* cfg) {
     if (!cfg) return fail(POLAR_E_INVAL, "cfg is NULL");
     if (cfg->log2n < 1 || cfg->log2n > POLAR_MAX_LOG2N)
         return fail(POLAR_E_INVAL, "log2n %d outside 1..%d", cfg->log2n, POLAR_MAX_LOG2N);
-    if (cfg->f_kind != POLAR_F_MINSUM && cfg->f_kind != POLAR_F_BOXPLUS) return fail(POLAR_E_INVAL, "unknown f_kind");
+    if (cfg->f_kind < POLAR_F_MINSUM || cfg->f_kind > POLAR_F_PHI_Q16) return fail(POLAR_E_INVAL, "unknown f_kind");
     if (!(cfg->p > 0.0 && cfg->p < 0.5)) return fail(POLAR_E_INVAL, "p must lie in (0, 1/2)");
     if (!cfg->frozen_mask) return fail(POLAR_E_INVAL, "frozen_mask is NULL");
     if (cfg->n_frames < 0 || cfg->frame0 < 0 || cfg->frame0 + cfg->n_frames > ((int64_t)1 << 32))
@@ -215,9 +216,9 @@ FerLayout layout(const polar_ctx* c, const polar_fer_cfg* cfg) {
 
 }  // namespace
 
-extern "C" int polar_fer_generate_bsc(int log2n, double p, const uint32_t* frozen_mask, uint64_t seed,
-                                      int64_t frame0, int n_frames, uint32_t* u, uint32_t* frozen_vals,
-                                      uint32_t* x_scratch, float* llr, void* stream) {
+extern "C" int polar_fer_generate_bsc(int log2n, double p, int fixed_point, const uint32_t* frozen_mask,
+                                      uint64_t seed, int64_t frame0, int n_frames, uint32_t* u,
+                                      uint32_t* frozen_vals, uint32_t* x_scratch, float* llr, void* stream) {
     if (log2n < 1 || log2n > POLAR_MAX_LOG2N) return fail(POLAR_E_INVAL, "log2n %d outside 1..%d", log2n, POLAR_MAX_LOG2N);
     if (!(p > 0.0 && p < 0.5)) return fail(POLAR_E_INVAL, "p must lie in (0, 1/2)");
     if (n_frames < 0 || frame0 < 0 || frame0 + n_frames > ((int64_t)1 << 32))
@@ -229,7 +230,10 @@ extern "C" int polar_fer_generate_bsc(int log2n, double p, const uint32_t* froze
     const int64_t wpf = wpf_of(log2n);
     const int64_t n = (int64_t)1 << log2n;
     const uint32_t th = (uint32_t)std::floor(p * 4294967296.0);
-    const float l0 = (float)std::log((1.0 - p) / p);
+    // fixed point: L0 in units of 2^-4, rounded half to even, saturated
+    const double l0d = std::log((1.0 - p) / p);
+    const float l0 = fixed_point ? (float)std::min(std::nearbyint(l0d * (1 << POLAR_FIXED_FRAC)), (double)POLAR_FIXED_MAX)
+                                 : (float)l0d;
     hipLaunchKernelGGL(k_gen_u, dim3(grid_of((wpf + 3) / 4 * n_frames)), dim3(256), 0, s, (uint32_t)seed,
                        (uint32_t)frame0, n_frames, log2n, wpf, frozen_mask, u, frozen_vals);
     hipError_t e = polar_dev_encode(log2n, n_frames, u, x_scratch, s);
@@ -275,8 +279,8 @@ extern "C" int polar_fer_bsc(polar_ctx* c, const polar_fer_cfg* cfg, void* works
     Plan p;
     for (int64_t done = 0; done < cfg->n_frames; done += L.batch) {
         const int nb = (int)std::min<int64_t>(L.batch, cfg->n_frames - done);
-        rc = polar_fer_generate_bsc(log2n, cfg->p, cfg->frozen_mask, cfg->seed, cfg->frame0 + done, nb, u, vals, x,
-                                    llr, stream);
+        rc = polar_fer_generate_bsc(log2n, cfg->p, cfg->f_kind >= POLAR_F_MINSUM_Q16, cfg->frozen_mask, cfg->seed,
+                                    cfg->frame0 + done, nb, u, vals, x, llr, stream);
         if (rc) return rc;
         fr.assign((size_t)nb, polar_frame{});
         for (int k = 0; k < nb; ++k) {

@@ -236,7 +236,7 @@ int validate_frames(const polar_frame* frames, int n_frames) {
         const polar_frame& f = frames[i];
         if (f.log2n < 1 || f.log2n > POLAR_MAX_LOG2N)
             return fail(POLAR_E_INVAL, "frame %d: log2n %d outside 1..%d", i, f.log2n, POLAR_MAX_LOG2N);
-        if (f.f_kind != POLAR_F_MINSUM && f.f_kind != POLAR_F_BOXPLUS)
+        if (f.f_kind < POLAR_F_MINSUM || f.f_kind > POLAR_F_PHI_Q16)
             return fail(POLAR_E_INVAL, "frame %d: unknown f_kind %d", i, f.f_kind);
         if (!f.llr || !f.frozen_mask || !f.frozen_vals || !f.u_hat)
             return fail(POLAR_E_INVAL, "frame %d: NULL buffer", i);
@@ -288,6 +288,8 @@ LaunchCfg group_cfg(const polar_ctx* c, int fk, bool dump, const SizeHist& h, bo
     if (!c->prune) cfg.prune = 0;
     else if (cfg.prune < 0) cfg.prune = 1;
     if (dump || !cfg.prune) cfg.cutover = 12;
+    // variants other than cutover 12 are built for the FP32 check updates only
+    if (!polar_dev_variant_built(cfg.cutover, fk, cfg.prune, dump ? 1 : 0)) cfg.cutover = 12;
     // at most the workgroups that can be resident at once
     const int cap = c->n_cu * occupancy(c, cfg.cutover, fk, dump, cfg.waves, cfg.prune != 0);
     const int asked = cfg.slots;
@@ -345,13 +347,13 @@ void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool
                const LaunchCfg* force, bool per_frame) {
     // order: by (f_kind, leaf dump), inside a group most work (largest N)
     // first, ties in submission order: a stable counting sort over the
-    // 4 x 25 keys (no allocation once the plan's vectors have the capacity)
+    // 8 x 25 keys (no allocation once the plan's vectors have the capacity)
     constexpr int NL = POLAR_MAX_LOG2N + 1;
     auto key = [&](int i) { return frames[i].f_kind * 2 + (frames[i].leaf_llr ? 1 : 0); };
     auto bucket = [&](int i) { return key(i) * NL + (POLAR_MAX_LOG2N - frames[i].log2n); };
-    int start[4 * NL + 1] = {};
+    int start[8 * NL + 1] = {};
     for (int i = 0; i < n_frames; ++i) ++start[bucket(i) + 1];
-    for (int b = 0; b < 4 * NL; ++b) start[b + 1] += start[b];
+    for (int b = 0; b < 8 * NL; ++b) start[b + 1] += start[b];
     std::vector<int>& order = p.order;
     order.resize((size_t)n_frames);
     for (int i = 0; i < n_frames; ++i) order[(size_t)start[bucket(i)]++] = i;
@@ -715,6 +717,13 @@ extern "C" int polar_sc_decode_batch(polar_ctx* c, const polar_frame* frames, in
 
 extern "C" int polar_sc_decode_plain(polar_ctx* c, const polar_frame* frames, int n_frames, void* stream) {
     return decode_impl(c, frames, n_frames, stream, true);
+}
+
+extern "C" int polar_debug_phi_table(float* out, void* stream) {
+    if (!out) return fail(POLAR_E_INVAL, "out is NULL");
+    hipError_t e = polar_dev_phi_table(out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "phi table launch");
+    return ok();
 }
 
 extern "C" int polar_debug_lane_selftest(uint32_t* out, void* stream) {

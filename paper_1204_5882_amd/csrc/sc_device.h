@@ -45,40 +45,58 @@ struct DecodeLaunch {
 extern "C" {
 hipError_t polar_dev_launch_decode(const DecodeLaunch* a);
 // decoder variants (one translation unit each)
-hipError_t polar_dec_c12_ms(const DecodeLaunch* a);
-hipError_t polar_dec_c12_ms_dump(const DecodeLaunch* a);
-hipError_t polar_dec_c12_ms_prune(const DecodeLaunch* a);
-hipError_t polar_dec_c12_ms_prune_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c10_bp_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c10_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c11_bp_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c11_ms_prune(const DecodeLaunch* a);
 hipError_t polar_dec_c12_bp(const DecodeLaunch* a);
 hipError_t polar_dec_c12_bp_dump(const DecodeLaunch* a);
 hipError_t polar_dec_c12_bp_prune(const DecodeLaunch* a);
 hipError_t polar_dec_c12_bp_prune_dump(const DecodeLaunch* a);
-hipError_t polar_dec_c11_ms_prune(const DecodeLaunch* a);
-hipError_t polar_dec_c11_bp_prune(const DecodeLaunch* a);
-hipError_t polar_dec_c10_ms_prune(const DecodeLaunch* a);
-hipError_t polar_dec_c10_bp_prune(const DecodeLaunch* a);
-hipError_t polar_dec_c9_ms_prune(const DecodeLaunch* a);
-hipError_t polar_dec_c9_bp_prune(const DecodeLaunch* a);
-hipError_t polar_dec_c8_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c12_ms(const DecodeLaunch* a);
+hipError_t polar_dec_c12_ms_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c12_ms_prune_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_phi(const DecodeLaunch* a);
+hipError_t polar_dec_c12_phi_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_phi_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c12_phi_prune_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_q16(const DecodeLaunch* a);
+hipError_t polar_dec_c12_q16_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_q16_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c12_q16_prune_dump(const DecodeLaunch* a);
 hipError_t polar_dec_c8_bp_prune(const DecodeLaunch* a);
-int polar_dec_c12_ms_occupancy(int waves, int small_log2n);
-int polar_dec_c12_ms_dump_occupancy(int waves, int small_log2n);
-int polar_dec_c12_ms_prune_occupancy(int waves, int small_log2n);
-int polar_dec_c12_ms_prune_dump_occupancy(int waves, int small_log2n);
+hipError_t polar_dec_c8_ms_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c9_bp_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c9_ms_prune(const DecodeLaunch* a);
+int polar_dec_c10_bp_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c10_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c11_bp_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c11_ms_prune_occupancy(int waves, int small_log2n);
 int polar_dec_c12_bp_occupancy(int waves, int small_log2n);
 int polar_dec_c12_bp_dump_occupancy(int waves, int small_log2n);
 int polar_dec_c12_bp_prune_occupancy(int waves, int small_log2n);
 int polar_dec_c12_bp_prune_dump_occupancy(int waves, int small_log2n);
-int polar_dec_c11_ms_prune_occupancy(int waves, int small_log2n);
-int polar_dec_c11_bp_prune_occupancy(int waves, int small_log2n);
-int polar_dec_c10_ms_prune_occupancy(int waves, int small_log2n);
-int polar_dec_c10_bp_prune_occupancy(int waves, int small_log2n);
-int polar_dec_c9_ms_prune_occupancy(int waves, int small_log2n);
-int polar_dec_c9_bp_prune_occupancy(int waves, int small_log2n);
-int polar_dec_c8_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c12_ms_occupancy(int waves, int small_log2n);
+int polar_dec_c12_ms_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c12_ms_prune_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_phi_occupancy(int waves, int small_log2n);
+int polar_dec_c12_phi_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_phi_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c12_phi_prune_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_q16_occupancy(int waves, int small_log2n);
+int polar_dec_c12_q16_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_q16_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c12_q16_prune_dump_occupancy(int waves, int small_log2n);
 int polar_dec_c8_bp_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c8_ms_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c9_bp_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c9_ms_prune_occupancy(int waves, int small_log2n);
 
 int polar_dev_cutover_supported(int c);
+// 1 if the decoder variant (cutover, check-update kind, pruning, leaf dump) is built.
+int polar_dev_variant_built(int cutover, int fk, int prune, int dump);
 // Frames per workgroup a workgroup of `waves` wavefronts can decode at once,
 // one per wavefront, for frames of 2^log2n <= 2^cutover leaves (LDS bound).
 int polar_dev_max_fwg(int cutover, int log2n, int waves);
@@ -91,4 +109,5 @@ int polar_dev_waves_supported(int w);
 int64_t polar_dev_slot_bytes(int log2n, int cutover);
 hipError_t polar_dev_encode(int log2n, int n_frames, const uint32_t* u, uint32_t* x, hipStream_t s);
 hipError_t polar_dev_lane_selftest(uint32_t* out, hipStream_t s);
+hipError_t polar_dev_phi_table(float* out, hipStream_t s);
 }

@@ -80,80 +80,81 @@ __global__ void k_lane_selftest(uint32_t* out) {
     out[15 * 64 + l] = (uint32_t)(lt >> 32);
 }
 
+// The phi table of the fixed-point check update, as every workgroup of a
+// FK = 3 decoder builds it (diagnostics).
+__global__ void k_phi_table(float* out) {
+    phi_table_init();
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < PHI_LEN; i += (int)blockDim.x) out[i] = g_phi[i];
+}
+
 }  // namespace polar_dev
 
 using namespace polar_dev;
 
+extern "C" hipError_t polar_dev_phi_table(float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_phi_table, dim3(1), dim3(256), 0, s, out);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Every built decoder variant: (cutover, check-update kind, pruning, leaf
+// dump) and its launch and occupancy functions.
+struct Variant {
+    int cutover, fk, prune, dump;
+    hipError_t (*launch)(const DecodeLaunch*);
+    int (*occupancy)(int, int);
+};
+
+constexpr Variant kVariants[] = {
+    {10, 1, 1, 0, polar_dec_c10_bp_prune, polar_dec_c10_bp_prune_occupancy},
+    {10, 0, 1, 0, polar_dec_c10_ms_prune, polar_dec_c10_ms_prune_occupancy},
+    {11, 1, 1, 0, polar_dec_c11_bp_prune, polar_dec_c11_bp_prune_occupancy},
+    {11, 0, 1, 0, polar_dec_c11_ms_prune, polar_dec_c11_ms_prune_occupancy},
+    {12, 1, 0, 0, polar_dec_c12_bp, polar_dec_c12_bp_occupancy},
+    {12, 1, 0, 1, polar_dec_c12_bp_dump, polar_dec_c12_bp_dump_occupancy},
+    {12, 1, 1, 0, polar_dec_c12_bp_prune, polar_dec_c12_bp_prune_occupancy},
+    {12, 1, 1, 1, polar_dec_c12_bp_prune_dump, polar_dec_c12_bp_prune_dump_occupancy},
+    {12, 0, 0, 0, polar_dec_c12_ms, polar_dec_c12_ms_occupancy},
+    {12, 0, 0, 1, polar_dec_c12_ms_dump, polar_dec_c12_ms_dump_occupancy},
+    {12, 0, 1, 0, polar_dec_c12_ms_prune, polar_dec_c12_ms_prune_occupancy},
+    {12, 0, 1, 1, polar_dec_c12_ms_prune_dump, polar_dec_c12_ms_prune_dump_occupancy},
+    {12, 3, 0, 0, polar_dec_c12_phi, polar_dec_c12_phi_occupancy},
+    {12, 3, 0, 1, polar_dec_c12_phi_dump, polar_dec_c12_phi_dump_occupancy},
+    {12, 3, 1, 0, polar_dec_c12_phi_prune, polar_dec_c12_phi_prune_occupancy},
+    {12, 3, 1, 1, polar_dec_c12_phi_prune_dump, polar_dec_c12_phi_prune_dump_occupancy},
+    {12, 2, 0, 0, polar_dec_c12_q16, polar_dec_c12_q16_occupancy},
+    {12, 2, 0, 1, polar_dec_c12_q16_dump, polar_dec_c12_q16_dump_occupancy},
+    {12, 2, 1, 0, polar_dec_c12_q16_prune, polar_dec_c12_q16_prune_occupancy},
+    {12, 2, 1, 1, polar_dec_c12_q16_prune_dump, polar_dec_c12_q16_prune_dump_occupancy},
+    {8, 1, 1, 0, polar_dec_c8_bp_prune, polar_dec_c8_bp_prune_occupancy},
+    {8, 0, 1, 0, polar_dec_c8_ms_prune, polar_dec_c8_ms_prune_occupancy},
+    {9, 1, 1, 0, polar_dec_c9_bp_prune, polar_dec_c9_bp_prune_occupancy},
+    {9, 0, 1, 0, polar_dec_c9_ms_prune, polar_dec_c9_ms_prune_occupancy},
+};
+
+const Variant* find_variant(int cutover, int fk, int prune, int dump) {
+    for (const Variant& v : kVariants)
+        if (v.cutover == cutover && v.fk == fk && v.prune == (prune ? 1 : 0) && v.dump == (dump ? 1 : 0)) return &v;
+    return nullptr;
+}
+
+}  // namespace
+
 extern "C" hipError_t polar_dev_launch_decode(const DecodeLaunch* a) {
     if (a->waves != 4 && a->waves != 8) return hipErrorInvalidValue;
-    const int v = (a->fk ? 4 : 0) + (a->prune ? 2 : 0) + (a->dump ? 1 : 0);
-    switch (a->cutover) {
-        case 12:
-            switch (v) {
-                case 0: return polar_dec_c12_ms(a);
-                case 1: return polar_dec_c12_ms_dump(a);
-                case 2: return polar_dec_c12_ms_prune(a);
-                case 3: return polar_dec_c12_ms_prune_dump(a);
-                case 4: return polar_dec_c12_bp(a);
-                case 5: return polar_dec_c12_bp_dump(a);
-                case 6: return polar_dec_c12_bp_prune(a);
-                case 7: return polar_dec_c12_bp_prune_dump(a);
-            }
-            break;
-        // smaller register-resident subtrees: production path only
-        case 11:
-            if (v == 2) return polar_dec_c11_ms_prune(a);
-            if (v == 6) return polar_dec_c11_bp_prune(a);
-            break;
-        case 10:
-            if (v == 2) return polar_dec_c10_ms_prune(a);
-            if (v == 6) return polar_dec_c10_bp_prune(a);
-            break;
-        case 9:
-            if (v == 2) return polar_dec_c9_ms_prune(a);
-            if (v == 6) return polar_dec_c9_bp_prune(a);
-            break;
-        case 8:
-            if (v == 2) return polar_dec_c8_ms_prune(a);
-            if (v == 6) return polar_dec_c8_bp_prune(a);
-            break;
-    }
-    return hipErrorInvalidValue;
+    const Variant* v = find_variant(a->cutover, a->fk, a->prune, a->dump);
+    return v ? v->launch(a) : hipErrorInvalidValue;
 }
 
 extern "C" int polar_dev_occupancy(int cutover, int fk, int prune, int dump, int waves, int small_log2n) {
-    const int v = (fk ? 4 : 0) + (prune ? 2 : 0) + (dump ? 1 : 0);
-    switch (cutover) {
-        case 12:
-            switch (v) {
-                case 0: return polar_dec_c12_ms_occupancy(waves, small_log2n);
-                case 1: return polar_dec_c12_ms_dump_occupancy(waves, small_log2n);
-                case 2: return polar_dec_c12_ms_prune_occupancy(waves, small_log2n);
-                case 3: return polar_dec_c12_ms_prune_dump_occupancy(waves, small_log2n);
-                case 4: return polar_dec_c12_bp_occupancy(waves, small_log2n);
-                case 5: return polar_dec_c12_bp_dump_occupancy(waves, small_log2n);
-                case 6: return polar_dec_c12_bp_prune_occupancy(waves, small_log2n);
-                case 7: return polar_dec_c12_bp_prune_dump_occupancy(waves, small_log2n);
-            }
-            break;
-        case 11:
-            if (v == 2) return polar_dec_c11_ms_prune_occupancy(waves, small_log2n);
-            if (v == 6) return polar_dec_c11_bp_prune_occupancy(waves, small_log2n);
-            break;
-        case 10:
-            if (v == 2) return polar_dec_c10_ms_prune_occupancy(waves, small_log2n);
-            if (v == 6) return polar_dec_c10_bp_prune_occupancy(waves, small_log2n);
-            break;
-        case 9:
-            if (v == 2) return polar_dec_c9_ms_prune_occupancy(waves, small_log2n);
-            if (v == 6) return polar_dec_c9_bp_prune_occupancy(waves, small_log2n);
-            break;
-        case 8:
-            if (v == 2) return polar_dec_c8_ms_prune_occupancy(waves, small_log2n);
-            if (v == 6) return polar_dec_c8_bp_prune_occupancy(waves, small_log2n);
-            break;
-    }
-    return 0;
+    const Variant* v = find_variant(cutover, fk, prune, dump);
+    return v ? v->occupancy(waves, small_log2n) : 0;
+}
+
+extern "C" int polar_dev_variant_built(int cutover, int fk, int prune, int dump) {
+    return find_variant(cutover, fk, prune, dump) != nullptr;
 }
 
 extern "C" int polar_dev_max_fwg(int cutover, int log2n, int waves) {

@@ -181,17 +181,23 @@ __device__ __forceinline__ float f_minsum(float a, float b) {
 // Exact check update 2 atanh(tanh(a/2) tanh(b/2)) (the phi = log tanh(x/2)
 // form of Section 4) in FP32, on magnitudes A = |a|, B = |b|, m = min(A, B):
 //   m <= 1:  r = log1p(2t / (1 - t)),  t = tanh(A/2) tanh(B/2) <= tanh(1/2)^2,
-//            tanh(x/2) = expm1(x) / (expm1(x) + 2);
+//            which with tanh(x/2) = E / (E + 2), E = expm1(x), is exactly
+//            r = log1p(Ea Eb / (Ea + Eb + 2))  (no 1 - t cancellation);
 //   m >  1:  r = m + log1p(e^-(A+B)) - log1p(e^-|A-B|)   (r >= 1 - ln 2).
 // Each form is accurate where it is selected.  Everything is straight-line
-// code on the hardware exp2 / log2 (no library calls): both forms are
-// evaluated and one is selected, so the wavefront never diverges here (the
-// decoder's ballots and lane shifts need a fully active wavefront).
+// code on the hardware exp2 / log2 / reciprocal (no library calls, no IEEE
+// division sequence: the reciprocal is within 1 ulp, far inside the 1e-5
+// LLR tolerance): both forms are evaluated and one is selected, so the
+// wavefront never diverges here (the decoder's ballots and lane shifts need a
+// fully active wavefront).
 __device__ __forceinline__ float hw_exp(float x) {   // e^x
     return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
 }
 __device__ __forceinline__ float hw_log(float x) {   // ln x
     return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+}
+__device__ __forceinline__ float hw_rcp(float x) {   // 1 / x, normal x
+    return __builtin_amdgcn_rcpf(x);
 }
 // expm1(x) for x >= 0: Taylor series to x^9/9! below 1/2 (truncation error
 // < 3e-9 relative), e^x - 1 above (no cancellation there).
@@ -213,7 +219,7 @@ __device__ __forceinline__ float expm1_pos(float x) {
 __device__ __forceinline__ float log1p_pos(float z) {
     const float u = 1.0f + z;
     const float d = u - 1.0f;
-    const float r = hw_log(u) * (z / d);
+    const float r = hw_log(u) * (z * hw_rcp(d));  // d = 0 or d >= 2^-24: normal
     return d == 0.0f ? z : r;
 }
 __device__ __forceinline__ float f_boxplus(float a, float b) {
@@ -222,8 +228,7 @@ __device__ __forceinline__ float f_boxplus(float a, float b) {
     // tanh form (argument clamped: tanh(x/2) is 1 in FP32 beyond x = 40)
     const float ea = expm1_pos(fminf(A, 40.0f));
     const float eb = expm1_pos(fminf(B, 40.0f));
-    const float t = (ea / (ea + 2.0f)) * (eb / (eb + 2.0f));
-    const float r_small = log1p_pos(2.0f * t / (1.0f - t));
+    const float r_small = log1p_pos(ea * eb * hw_rcp(ea + eb + 2.0f));
     // log form
     const float r_large = m + log1p_pos(hw_exp(-(A + B))) - log1p_pos(hw_exp(-fabsf(A - B)));
     const float r = (m <= 1.0f) ? r_small : r_large;
@@ -231,15 +236,68 @@ __device__ __forceinline__ float f_boxplus(float a, float b) {
     return __uint_as_float(__float_as_uint(r) | s);
 }
 
+// Fixed point (Section 4: the paper's decoder keeps LLRs in fixed point and
+// takes the check update from a table of phi(x) = -ln tanh(x/2), its main
+// optimization).  LLRs are integers in units of 2^-4, saturated to +-32767,
+// held in FP32 registers (exact: every value is an integer below 2^24, and
+// min, add and compare of such floats are the integer operations).
+//   FK = 2, saturating min-sum:  f = sign(a) sign(b) min(|a|, |b|)
+//   FK = 3, phi table:           f = sign(a) sign(b) min(T[min(T[|a|] + T[|b|], 255)], |a|, |b|)
+//                                (T[i] = 0 from i = 67 on, so beyond the table
+//                                the lookup is 0; the min with |a|, |b| holds
+//                                because the exact update never exceeds either
+//                                magnitude, and stands in for T[0] = phi(0))
+//   both: g = sat(b + (1 - 2u) a)
+constexpr float FIXED_MAX = 32767.0f;
+constexpr int PHI_LEN = 256;
+
+// The workgroup's copy of T (kernels with FK = 3 only: LDS is allocated only
+// in kernels that use it).
+static __shared__ float g_phi[PHI_LEN];
+
+// T[i] = round(phi(i / 16) * 16) (half up), capped at 32767, T[0] = 32767,
+// with phi(x) = log1p(2 / expm1(x)) (the same function as -ln tanh(x/2),
+// without cancellation for large x), in FP64.  Every thread of the workgroup
+// must call it; the caller synchronises before use.
+__device__ __forceinline__ void phi_table_init() {
+    for (int i = (int)threadIdx.x; i < PHI_LEN; i += (int)blockDim.x) {
+        float t = FIXED_MAX;
+        if (i > 0) {
+            const double r = floor(log1p(2.0 / expm1((double)i * 0.0625)) * 16.0 + 0.5);
+            t = r > 32767.0 ? FIXED_MAX : (float)r;
+        }
+        g_phi[i] = t;
+    }
+}
+
+__device__ __forceinline__ float f_phi(float a, float b) {
+    const float A = fabsf(a), B = fabsf(b);
+    const float m = fminf(A, B);
+    const int ia = min((int)A, PHI_LEN - 1), ib = min((int)B, PHI_LEN - 1);
+    const int is = (int)fminf(g_phi[ia] + g_phi[ib], (float)(PHI_LEN - 1));
+    const float r = fminf(g_phi[is], m);
+    const uint32_t s = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
+    return __uint_as_float(__float_as_uint(r) | s);
+}
+
 template <int FK>
 __device__ __forceinline__ float fupd(float a, float b) {
-    if constexpr (FK == 0) return f_minsum(a, b);
-    else return f_boxplus(a, b);
+    if constexpr (FK == 0 || FK == 2) return f_minsum(a, b);
+    else if constexpr (FK == 1) return f_boxplus(a, b);
+    else return f_phi(a, b);
+}
+
+// The variable update's sum, saturated for the fixed-point kinds.
+template <int FK>
+__device__ __forceinline__ float gsat(float x) {
+    if constexpr (FK >= 2) return __builtin_amdgcn_fmed3f(x, -FIXED_MAX, FIXED_MAX);
+    else return x;
 }
 
 // g = b + (1 - 2u) a with the sign of a flipped by sgn (0 or 0x80000000).
+template <int FK>
 __device__ __forceinline__ float gupd(float a, float b, uint32_t sgn) {
-    return b + __uint_as_float(__float_as_uint(a) ^ sgn);
+    return gsat<FK>(b + __uint_as_float(__float_as_uint(a) ^ sgn));
 }
 
 // Rate-1 nodes (no frozen leaf).  In a rate-1 node SC's partial sums equal
@@ -255,9 +313,15 @@ __device__ __forceinline__ float gupd(float a, float b, uint32_t sgn) {
 //            node of size 2^L at or above 1.
 // Below the floor the decoder descends into the node like any other, which
 // is SC by construction; its children are checked again.
+//   saturating min-sum (FK = 2): as min-sum (a saturated sum of two terms of
+//            the sign of b keeps that sign and is nonzero);
+//   phi table (FK = 3): the table update can round a nonzero result to 0
+//            anywhere, so no floor holds: rate-1 nodes are always descended.
 template <int FK>
 __host__ __device__ constexpr float rate1_floor(int L) {
-    return FK == 0 ? 0.0f : 1.0f + 0.69314718f * (float)L + 0.01f;
+    return (FK == 0 || FK == 2) ? 0.0f
+           : FK == 1            ? 1.0f + 0.69314718f * (float)L + 0.01f
+                                : __builtin_inff();
 }
 
 // |x| <= floor, evaluated on the magnitude bits (non-negative floats order
@@ -316,19 +380,19 @@ __device__ __forceinline__ uint32_t sel_lanes(uint64_t lanes, uint32_t x, uint32
 // being a rate-0 node whose partial sums are w[log h] on its lanes.  The node's
 // partial sums are the frozen values re-encoded (w[log M]), all flipped when
 // the last bit is 1 (row M-1 of G_M is all ones).
-template <int H, int M>
+template <int H, int M, int FK>
 __device__ __forceinline__ float rep_chain(float x, const Blk& B) {
     if constexpr (H == 0) {
         return x;
     } else {
-        const float y = x + __uint_as_float(lane_up<H>(__float_as_uint(x) ^ B.w[ilog2<H>()]));
-        return rep_chain<H / 2, M>(y, B);
+        const float y = gsat<FK>(x + __uint_as_float(lane_up<H>(__float_as_uint(x) ^ B.w[ilog2<H>()])));
+        return rep_chain<H / 2, M, FK>(y, B);
     }
 }
 
-template <int M, bool DUMP>
+template <int M, int FK, bool DUMP>
 __device__ __forceinline__ void rep_node(float a, int O, Blk& B) {
-    const float last = rep_chain<M / 2, M>(a, B);
+    const float last = rep_chain<M / 2, M, FK>(a, B);
     const int il = O + M - 1;
     if (DUMP && lane_id() == il) {
         B.leaf = last;
@@ -411,7 +475,7 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
             B.has_leaf = true;
         }
         return dec_sign(a);
-    } else if constexpr (P == 0 && FK == 0 && M > 2) {
+    } else if constexpr (P == 0 && (FK == 0 || FK == 2) && M > 2) {
         // (a 2-leaf rate-1 node is cheaper as plain f, g and two decisions
         // in vector registers than as two ballots and a scalar round trip)
         static_assert(M <= 32, "three-state words are 32 bits");
@@ -420,7 +484,7 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
         const uint64_t bits = (uint64_t)r1_bits<M>(S, Z) << O;
         return lane_bit(bits) ? SIGN : 0u;
     } else if constexpr (P == (ALL >> 1)) {
-        const float last = rep_chain<M / 2, M>(a, B);  // repetition
+        const float last = rep_chain<M / 2, M, FK>(a, B);  // repetition
         const int il = O + M - 1;
         if (DUMP && lane_id() == il) {
             B.leaf = last;
@@ -433,7 +497,7 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
         constexpr uint64_t LO = ones64(H);
         const float c = fupd<FK>(a, lane_downf<H>(a));
         const uint32_t bl = sl_node<H, (P & LO), FK, DUMP>(c, O, B);
-        const float d = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bl));
+        const float d = gsat<FK>(a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bl)));
         const uint32_t br = sl_node<H, (P >> H), FK, DUMP>(d, O + H, B);
         return sel_lanes(left_lanes<H>(), bl ^ lane_down<H>(br), br);
     }
@@ -540,7 +604,7 @@ template <int M, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void blk_node(float a, int O, Blk& B) {
     // (64-leaf cases only for min-sum without the leaf dump: with box-plus's
     // longer f, or the dump, they exceed the register budget)
-    if constexpr (PRUNE && M == 64 && FK == 0 && !DUMP) {
+    if constexpr (PRUNE && M == 64 && (FK == 0 || FK == 2) && !DUMP) {
         uint32_t bn;
         bool known = true;
         switch (B.F) {
@@ -608,7 +672,7 @@ __device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
                 if (side == 0) {
                     c = fupd<FK>(a, lane_downf<H>(a));  // left child, lanes [O, O + H)
                 } else {
-                    c = a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ B.beta));  // right child
+                    c = gsat<FK>(a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ B.beta)));  // right child
                 }
                 blk_node<H, FK, PRUNE, DUMP>(c, O + side * H, B);
             }
@@ -616,7 +680,7 @@ __device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
         } else if (type == 1) {
             B.beta = sel_lanes(ones64(M) << O, B.w[LG], B.beta);
         } else if (type == 3) {
-            rep_node<M, DUMP>(a, O, B);
+            rep_node<M, FK, DUMP>(a, O, B);
         } else {
             B.beta = sel_lanes(ones64(M) << O, dec_sign(a), B.beta);
         }
@@ -703,7 +767,7 @@ __device__ __forceinline__ void level_step(Lv<C>& v, int op, int b, uint64_t acc
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             const uint32_t sgn = (uint32_t)((x >> k) & 1ull) << 31;
-            lv_set<L, C>(v, k, gupd(lv_get<L + 1, C>(v, k), lv_get<L + 1, C>(v, k + E), sgn));
+            lv_set<L, C>(v, k, gupd<FK>(lv_get<L + 1, C>(v, k), lv_get<L + 1, C>(v, k + E), sgn));
         }
     }
 }
@@ -939,7 +1003,7 @@ __device__ __forceinline__ void sweep_f(const float* __restrict__ in, int64_t ha
 // 64 words each, bit k of word (s, lane) = element s*2^C + k*64 + lane).
 // Element j reads bit (j >> 6) mod 2^(C-6) of word (j >> C)*64 + (j & 63);
 // the 4 elements of a lane use 4 consecutive words.
-template <int C>
+template <int C, int FK>
 __device__ __forceinline__ float4 g4(float4 a, float4 b, const uint64_t* __restrict__ beta, int64_t j) {
     constexpr int E = 1 << (C - 6);
     const uint64_t* w = beta + (j >> C) * 64 + (j & 63);
@@ -947,11 +1011,11 @@ __device__ __forceinline__ float4 g4(float4 a, float4 b, const uint64_t* __restr
     const ulonglong2 w23 = *reinterpret_cast<const ulonglong2*>(w + 2);
     const int k = (int)((j >> 6) & (E - 1));
     const auto sg = [k](uint64_t x) { return (uint32_t)((x >> k) & 1ull) << 31; };
-    return make_float4(gupd(a.x, b.x, sg(w01.x)), gupd(a.y, b.y, sg(w01.y)), gupd(a.z, b.z, sg(w23.x)),
-                       gupd(a.w, b.w, sg(w23.y)));
+    return make_float4(gupd<FK>(a.x, b.x, sg(w01.x)), gupd<FK>(a.y, b.y, sg(w01.y)),
+                       gupd<FK>(a.z, b.z, sg(w23.x)), gupd<FK>(a.w, b.w, sg(w23.y)));
 }
 
-template <int C>
+template <int C, int FK>
 __device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t half,
                                         const uint64_t* __restrict__ beta, float* __restrict__ out,
                                         int wave, int nw) {
@@ -969,12 +1033,12 @@ __device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t ha
 #pragma unroll
         for (int i = 0; i < SWEEP_UNROLL; ++i) {
             const int64_t j = (r + i * nw) * 256 + l4;
-            st4(out + j, g4<C>(x[i], y[i], beta, j));
+            st4(out + j, g4<C, FK>(x[i], y[i], beta, j));
         }
     }
     for (; r < rows; r += nw) {
         const int64_t j = r * 256 + l4;
-        st4(out + j, g4<C>(ld4(in + j), ld4(in + j + half), beta, j));
+        st4(out + j, g4<C, FK>(ld4(in + j), ld4(in + j + half), beta, j));
     }
 }
 
@@ -991,7 +1055,7 @@ __device__ __forceinline__ void sweep2(const float* __restrict__ in, int64_t h, 
     const int64_t q = h >> 1;
     const int64_t rows = q >> 8;
     const auto first = [&](float4 a, float4 b, int64_t j) -> float4 {
-        if constexpr (G) return g4<C>(a, b, beta, j);
+        if constexpr (G) return g4<C, FK>(a, b, beta, j);
         else return f4<FK>(a, b);
     };
     int64_t r = row_here(wave);
@@ -1091,7 +1155,7 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
             // (for the two deepest g levels the left sibling's partial sums
             // are the last one or two subtrees', read from their LDS copy)
             if (t == 0) {
-                sweep_g<C>(level(dp), half, lbeta, lds, wave, W);
+                sweep_g<C, FK>(level(dp), half, lbeta, lds, wave, W);
             } else if (t == 1) {
                 sweep2<C, FK, true>(level(dp), half, lbeta, level(D - t), lds, wave, W);
             } else {
@@ -1200,6 +1264,7 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __rest
     float* lds = lds_all;
     float* tier = lds_all + LDS_SUB;  // LLR levels of sizes 2^(C+1) and 2^(C+2)
     uint8_t* wg_slot = slots + (int64_t)blockIdx.x * slot_bytes;
+    if constexpr (FK == 3) phi_table_init();  // the barrier below orders it
     while (true) {
         if (threadIdx.x == 0) s_frame = (int)atomicAdd(counter, 1u);
         __syncthreads();
@@ -1233,6 +1298,10 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode_small(const FrameDesc* 
                                                              unsigned* __restrict__ counter,
                                                              unsigned long long* prof, uint32_t* done, int region) {
     extern __shared__ float lds_dyn[];
+    if constexpr (FK == 3) {
+        phi_table_init();
+        __syncthreads();
+    }
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     float* mine = lds_dyn + wave * region;
     for (int g = wave_draw(counter); g < n_frames; g = wave_draw(counter)) {

@@ -27,6 +27,10 @@ POLAR_E_CANCELLED = -5
 
 POLAR_F_MINSUM = 0
 POLAR_F_BOXPLUS = 1
+POLAR_F_MINSUM_Q16 = 2
+POLAR_F_PHI_Q16 = 3
+POLAR_FIXED_FRAC = 4
+POLAR_FIXED_MAX = 32767
 POLAR_MAX_LOG2N = 24
 
 POLAR_OPT_PRUNE = 1
@@ -47,7 +51,7 @@ EXPORTED = [
     "polar_sc_decode_plain", "polar_sc_decode_batch_static", "polar_autotune", "polar_query_launch", "polar_tune_clear",
     "polar_tune_save", "polar_tune_load", "polar_serve_open", "polar_serve_submit", "polar_serve_poll",
     "polar_serve_pending", "polar_serve_stats", "polar_serve_cancel", "polar_serve_close", "polar_serve",
-    "polar_debug_lane_selftest", "polar_fer_generate_bsc", "polar_fer_workspace_bytes", "polar_fer_bsc",
+    "polar_debug_lane_selftest", "polar_debug_phi_table", "polar_fer_generate_bsc", "polar_fer_workspace_bytes", "polar_fer_bsc",
 ]
 
 
@@ -154,7 +158,8 @@ def load():
         "polar_serve_close": ([P], I),
         "polar_serve": ([P, P, NEXT_FN, DONE_FN, P], I),
         "polar_debug_lane_selftest": ([P, P], I),
-        "polar_fer_generate_bsc": ([I, ctypes.c_double, P, ctypes.c_uint64, I64, I, P, P, P, P, P], I),
+        "polar_debug_phi_table": ([P, P], I),
+        "polar_fer_generate_bsc": ([I, ctypes.c_double, I, P, ctypes.c_uint64, I64, I, P, P, P, P, P], I),
         "polar_fer_workspace_bytes": ([P, P], SZ),
         "polar_fer_bsc": ([P, P, P, SZ, P, P, P], I),
     }
@@ -224,7 +229,8 @@ def encode(log2n: int, u, x=None, n_frames: Optional[int] = None, stream=None):
     return x
 
 
-def fer_generate_bsc(log2n: int, p: float, frozen_mask, seed: int, frame0: int, n_frames: int, stream=None):
+def fer_generate_bsc(log2n: int, p: float, frozen_mask, seed: int, frame0: int, n_frames: int, fixed_point=False,
+                     stream=None):
     """Synthetic BSC frames on the device (the harness's generator): returns
     (u words, frozen-value words, LLRs) as torch tensors of shapes
     (n_frames, W), (n_frames, W), (n_frames, N)."""
@@ -236,10 +242,20 @@ def fer_generate_bsc(log2n: int, p: float, frozen_mask, seed: int, frame0: int, 
     vals = torch.empty_like(u)
     x = torch.empty_like(u)
     llr = torch.empty((n_frames, 1 << log2n), dtype=torch.float32, device=dev)
-    _check(load().polar_fer_generate_bsc(int(log2n), float(p), _ptr(frozen_mask), int(seed), int(frame0),
+    _check(load().polar_fer_generate_bsc(int(log2n), float(p), int(bool(fixed_point)), _ptr(frozen_mask),
+                                         int(seed), int(frame0),
                                          int(n_frames), _ptr(u), _ptr(vals), _ptr(x), _ptr(llr),
                                          _stream_handle(stream)))
     return u, vals, llr
+
+
+def phi_table(stream=None):
+    """The phi table of POLAR_F_PHI_Q16 as the device builds it (256 floats)."""
+    import torch
+
+    out = torch.empty(256, dtype=torch.float32, device="cuda")
+    _check(load().polar_debug_phi_table(_ptr(out), _stream_handle(stream)))
+    return out
 
 
 def lane_selftest(stream=None):

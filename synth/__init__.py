@@ -47,6 +47,14 @@ def biawgn_llr(x: np.ndarray, noise: np.ndarray, sigma: float) -> np.ndarray:
     return (2.0 * y / (sigma * sigma)).astype(np.float32)
 
 
+def fixed_point(llr, frac: int = 4, limit: int = 32767) -> np.ndarray:
+    """Input recipe for the fixed-point decoders: channel LLRs as integers in
+    units of 2^-frac (round half to even, saturated to +-limit), stored as
+    float32."""
+    q = np.clip(np.round(np.asarray(llr, np.float64) * (1 << frac)), -limit, limit)
+    return q.astype(np.float32)
+
+
 def bsc_z0(p: float) -> float:
     """Bhattacharyya parameter of BSC(p)."""
     return 2.0 * math.sqrt(p * (1.0 - p))

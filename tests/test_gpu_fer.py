@@ -87,3 +87,29 @@ def test_device_fer_equals_oracle_fer(log2n, p, nf, frames, frame0):
     torch.cuda.synchronize()
     assert res2 == res and np.array_equal(bit_err2.cpu().numpy(), bit_err.cpu().numpy())
     ctx.close()
+
+
+@pytest.mark.parametrize("fk", [2, 3])
+def test_device_fer_fixed_point_equals_oracle(fk):
+    """The harness with the fixed-point decoders (LLRs +-round(16 L0)):
+    the same per-frame errors as the oracle's integer decoder."""
+    import torch
+
+    from paper_1204_5882_amd import polar as lp
+
+    log2n, p, nf, frames = 11, 0.03, 600, 500
+    kind = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI}[fk]
+    mask, _, _ = oracle.frozen_set(log2n, synth.bsc_z0(p), nf)
+    _say(f"case: fixed-point generator and FER, f_kind={fk}")
+    u, vals, llr = lp.fer_generate_bsc(log2n, p, _mask_dev(mask), seed=9, frame0=0, n_frames=2, fixed_point=True)
+    torch.cuda.synchronize()
+    for k in range(2):
+        _, _, ollr, _ = fer.bsc_frame(9, k, log2n, p, mask, fixed_point=True)
+        assert np.array_equal(llr.cpu().numpy()[k], ollr)
+    ctx = lp.Ctx(0)
+    res, bit_err = ctx.fer_bsc(log2n, p, _mask_dev(mask), frames, seed=9, f_kind=fk)
+    torch.cuda.synchronize()
+    errs, bits, flags = fer.fer_bsc(9, 0, frames, log2n, p, mask, fixed_kind=kind)
+    assert res["frame_errors"] == errs and res["bit_errors"] == bits, (res, errs, bits)
+    assert np.array_equal((bit_err.cpu().numpy() > 0).astype(np.uint8), flags)
+    ctx.close()

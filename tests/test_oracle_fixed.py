@@ -114,4 +114,4 @@ def test_phi_table_update_converges_to_exact_boxplus():
 def test_quantize():
     q = oracle.quantize([0.03, -0.03, 1.0, -2047.99, 5000.0, -5000.0])
     assert list(q) == [0, 0, 16, -32768 + 1, 32767, -32767]
-    assert oracle.quantize([0.0625 * 3.5])[0] == 4  # half away from zero at 3.5 -> 4
+    assert list(oracle.quantize([0.0625 * 3.5, 0.0625 * 2.5])) == [4, 2]  # ties to even
