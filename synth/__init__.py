@@ -65,6 +65,32 @@ def biawgn_z0(sigma: float) -> float:
     return math.exp(-1.0 / (2.0 * sigma * sigma))
 
 
+def biawgn_channel(sigma: float, cells: int = 2000, span: float = 8.0) -> np.ndarray:
+    """BPSK over AWGN(sigma) as a finite symmetric channel (the input of the
+    degrading construction): the output magnitude |y| is cut into `cells`
+    equal cells over [0, 1 + span sigma), the last one open to infinity, and
+    cell k gives the pair (P(y in cell | +1), P(-y in cell | +1)) from the
+    Gaussian distribution function.  Returns (cells, 2) float64 pairs with
+    a >= b >= 0 summing to 1."""
+    edges = np.linspace(0.0, 1.0 + span * sigma, cells + 1)
+    edges[-1] = np.inf
+
+    r = sigma * math.sqrt(2.0)
+
+    def upper(t):  # P(Y > t | x = +1), Y ~ N(1, sigma^2)
+        return np.array([0.5 * math.erfc((v - 1.0) / r) if np.isfinite(v) else 0.0 for v in t])
+
+    def lower(t):  # P(Y <= t | x = +1)
+        return np.array([0.5 * math.erfc((1.0 - v) / r) if np.isfinite(v) else 0.0 for v in t])
+
+    a = upper(edges[:-1]) - upper(edges[1:])
+    b = lower(-edges[:-1]) - lower(-edges[1:])
+    a = np.maximum(a, 0.0)
+    b = np.minimum(np.maximum(b, 0.0), a)
+    w = np.stack([a, b], 1)
+    return w / w.sum()
+
+
 def bsc_capacity(p: float) -> float:
     h = -p * math.log2(p) - (1.0 - p) * math.log2(1.0 - p)
     return 1.0 - h
