@@ -392,12 +392,15 @@ def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, loads=SERVE_LOAD
 PAPER_TABLE1_BSC2 = {16: (0.935, 0.09, 10.9), 20: (0.963, 0.11, 9.5), 24: (0.980, 0.08, 8.3)}
 
 
-def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1, seed=12345):
-    """Largest code rate (frozen set by Bhattacharyya ranking) whose measured
-    SC frame error rate stays at or below the target, per N, by bisection on
-    the number K of information bits; each point decodes `frames` synthetic
-    BSC frames with the device harness (generation, decoding and error
-    counting on the GPU).  Efficiency beta = K / (N C)."""
+def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1, seed=12345,
+            construction="bhattacharyya", mu=32, f_kind=0):
+    """Largest code rate whose measured SC frame error rate stays at or below
+    the target, per N, by bisection on the number K of information bits;
+    each point decodes `frames` synthetic BSC frames with the device harness
+    (generation, decoding and error counting on the GPU).  Efficiency
+    beta = K / (N C).  The frozen set of each K freezes the N - K least
+    reliable channels, ranked by the Bhattacharyya parameters or by the
+    device's degrading construction (mu outputs per channel)."""
     import math
 
     cap = 1.0 + p * math.log2(p) + (1.0 - p) * math.log2(1.0 - p)
@@ -407,11 +410,28 @@ def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1,
     for log2n in sizes:
         n = 1 << log2n
         nfr = frames[log2n]
+        construct_ms = None
+        if construction == "degrade":
+            w0 = np.array([[1.0 - p, p]])
+            ws = torch.empty(lp.construct_workspace_bytes(log2n, mu, 1), dtype=torch.uint8, device=dev)
+            pe_dev = torch.empty(n, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lp.construct_degrade(log2n, w0, mu, pe=pe_dev, workspace=ws)
+            torch.cuda.synchronize()
+            construct_ms = round((time.perf_counter() - t0) * 1e3, 2)
+            pe = pe_dev.cpu().numpy()
+            del ws, pe_dev
 
-        def fer_at(k, nfr=nfr, log2n=log2n, n=n):
-            words, _, _ = lp.build_frozen_set(log2n, synth.bsc_z0(p), n - k, 0.1)
-            mdev = torch.from_numpy(words.view(np.int32).copy()).to(dev)
-            res, _ = ctx.fer_bsc(log2n, p, mdev, nfr, seed=seed)
+            def mask_words(k, pe=pe, log2n=log2n, n=n):
+                return lp.frozen_from_pe(log2n, pe, n - k, 0.1)[0]
+        else:
+            def mask_words(k, log2n=log2n, n=n):
+                return lp.build_frozen_set(log2n, synth.bsc_z0(p), n - k, 0.1)[0]
+
+        def fer_at(k, nfr=nfr, log2n=log2n):
+            mdev = torch.from_numpy(mask_words(k).view(np.int32).copy()).to(dev)
+            res, _ = ctx.fer_bsc(log2n, p, mdev, nfr, seed=seed, f_kind=f_kind)
             return res["frame_errors"] / nfr
 
         lo, hi = int(0.5 * cap * n), int(cap * n)
@@ -424,21 +444,27 @@ def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1,
                 hi = mid
             steps += 1
         # the operating point, timed
-        words, _, _ = lp.build_frozen_set(log2n, synth.bsc_z0(p), n - lo, 0.1)
-        mdev = torch.from_numpy(words.view(np.int32).copy()).to(dev)
+        mdev = torch.from_numpy(mask_words(lo).view(np.int32).copy()).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res, _ = ctx.fer_bsc(log2n, p, mdev, nfr, seed=seed + 1)
+        res, _ = ctx.fer_bsc(log2n, p, mdev, nfr, seed=seed + 1, f_kind=f_kind)
         wall = time.perf_counter() - t0
         paper = PAPER_TABLE1_BSC2.get(log2n)
-        out.append(dict(log2n=log2n, K=lo, rate=round(lo / n, 5), beta=round(lo / n / cap, 4),
-                        fer=round(res["frame_errors"] / nfr, 4), frames=nfr, bisection_steps=steps,
-                        harness_Mbit_s=round(nfr * n / wall / 1e6, 1),
-                        paper=None if paper is None else dict(beta=paper[0], fer=paper[1], Mbit_s=paper[2])))
+        pt = dict(log2n=log2n, K=lo, rate=round(lo / n, 5), beta=round(lo / n / cap, 4),
+                  fer=round(res["frame_errors"] / nfr, 4), frames=nfr, bisection_steps=steps,
+                  harness_Mbit_s=round(nfr * n / wall / 1e6, 1),
+                  paper=None if paper is None else dict(beta=paper[0], fer=paper[1], Mbit_s=paper[2]))
+        if construct_ms is not None:
+            pt["construct_ms"] = construct_ms
+        out.append(pt)
     ctx.close()
+    ranking = ("Bhattacharyya-ranked frozen set" if construction == "bhattacharyya" else
+               f"frozen set ranked by the device's degrading construction, mu={mu}")
+    arith = {0: "FP32 min-sum", 1: "FP32 exact box-plus", 2: "fixed-point saturating min-sum",
+             3: "fixed-point phi-table exact update"}[f_kind]
     return dict(channel=f"BSC p={p}", capacity=round(cap, 6), target_fer=target, rule="largest K with FER <= target "
-                "(Bhattacharyya-ranked frozen set, FP32 min-sum SC, fresh frames for the reported point)",
-                points=out, note="the paper's frozen sets come from density evolution, not Bhattacharyya ranking")
+                f"({ranking}, {arith} SC, fresh frames for the reported point)",
+                points=out, note="the paper's frozen sets come from density evolution [MT09]")
 
 
 def copy_bandwidth(torch, dev, mib=1024):
@@ -618,6 +644,9 @@ def main(argv=None):
     if not args.no_fer:
         print("[bench] FER / efficiency leg", file=sys.stderr, flush=True)
         out["fer"] = fer_leg(lp, torch, dev)
+        # the paper's arithmetic (fixed-point phi table) on sets from the
+        # degrading construction
+        out["fer_degrade_phi"] = fer_leg(lp, torch, dev, construction="degrade", f_kind=3)
 
     if not args.no_serve:
         print("[bench] serving leg", file=sys.stderr, flush=True)

@@ -62,6 +62,11 @@ extern "C" {
 
 #define POLAR_MAX_LOG2N 24
 
+/* Degrading construction: outputs kept per channel, and outputs of the
+   channel it starts from. */
+#define POLAR_CONSTRUCT_MAX_MU 64
+#define POLAR_CONSTRUCT_MAX_OUTPUTS 65536
+
 /* Message describing the last failing call made by this thread ("" if none). */
 const char* polar_last_error(void);
 
@@ -93,6 +98,63 @@ const char* polar_version(void);
  */
 int polar_build_frozen_set(int log2n, double z0, int64_t n_frozen, double fer_bound,
                            uint32_t* frozen_mask, double* r_out, int64_t* n_frozen_out);
+
+/*
+ * Frozen-set construction by channel degradation, on the device (Section 3
+ * freezes the least reliable synthetic channels; the paper's sets come from
+ * the density-evolution construction it cites [MT09], which it does not
+ * describe).  Every synthetic channel is carried as a finite binary-input
+ * symmetric channel and degraded to at most mu outputs after each
+ * polarization step (Tal and Vardy), merging outputs by binning the binary
+ * entropy of their posterior (Pedarsani, Hassani, Tal and Telatar).  Merging
+ * degrades, so each pe[i] is an upper bound on the error probability of the
+ * ML decision of u_i given y and u_0 .. u_{i-1}; on the BEC it is exact
+ * (Z_i / 2).
+ *
+ * A channel is a list of pairs (a_k, b_k), a_k = W(y_k|0) >= b_k = W(y_k|1)
+ * >= 0, one per conjugate output pair {y_k, y_k'} (W(y_k'|0) = b_k), summing
+ * to 1; BSC(p): {(1-p, p)}; BEC(e): {(1-e, 0), (e/2, e/2)}.  Index i applies
+ * the polarization step selected by its most significant bit first (as in
+ * polar_build_frozen_set): minus (a_i a_j + b_i b_j, a_i b_j + b_i a_j) over
+ * the ordered output pairs (i, j); plus (a_i a_j, b_i b_j) and
+ * (max(a_i b_j, b_i a_j), min(a_i b_j, b_i a_j)).  Merge: output k goes to
+ * bin min(mu-1, floor(mu h2(b_k / (a_k + b_k)))), bins sum their outputs in
+ * output order (minus: i m + j; plus: the two outputs of (i, j) at
+ * 2(i m + j) and 2(i m + j) + 1), occupied bins kept ascending; w0 itself is
+ * merged first.  pe[i] = the b of channel i's occupied bins added in
+ * ascending order.  Double precision, every product and sum rounded alone.
+ *
+ *   log2n      0 .. POLAR_MAX_LOG2N
+ *   w0         host, m0 pairs (a, b) as 2 m0 doubles, a >= b >= 0, summing
+ *              to 1 within 1e-12 (used as given: each step squares a
+ *              channel's total mass, so a w0 off 1 by d scales level-n
+ *              values by about 1 + 2^n d); copied before the call returns
+ *              (the call waits for the stream to reach the copy)
+ *   m0         1 .. POLAR_CONSTRUCT_MAX_OUTPUTS
+ *   mu         2 .. POLAR_CONSTRUCT_MAX_MU outputs kept per channel
+ *   workspace  device, 256-byte aligned, polar_construct_workspace_bytes
+ *              (2^(n-1) + 2^(n-2) channels of mu pairs: 12 GiB at n = 24,
+ *              mu = 64)
+ *   pe         device out, N doubles
+ * Work on the device is asynchronous on stream.  Errors: POLAR_E_INVAL
+ * (arguments, w0 not a channel), POLAR_E_NOMEM (workspace too small),
+ * POLAR_E_DEVICE.
+ */
+size_t polar_construct_workspace_bytes(int log2n, int mu, int m0); /* 0 on invalid arguments */
+int polar_construct_degrade(int log2n, const double* w0, int m0, int mu, void* workspace, size_t ws_bytes,
+                            double* pe, void* stream);
+
+/*
+ * Frozen set from per-channel error probabilities (host).  Channels are
+ * ranked by pe, largest first, exact ties freezing the lower index first.
+ *   n_frozen  >= 0: freeze exactly this many (<= N); -1: the union-bound rule
+ *             of Section 3, the largest information set whose pe add up
+ *             (best first, one at a time) to at most fer_bound
+ *   pe        host, N doubles in [0, 1]
+ *   frozen_mask host out, max(1, N/32) words, 1 = frozen; n_frozen_out host out or NULL
+ */
+int polar_frozen_from_pe(int log2n, const double* pe, int64_t n_frozen, double fer_bound,
+                         uint32_t* frozen_mask, int64_t* n_frozen_out);
 
 /*
  * x = u G_N over GF(2) with G_N the n-fold Kronecker power of [[1,0],[1,1]],

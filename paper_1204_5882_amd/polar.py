@@ -42,6 +42,8 @@ POLAR_OPT_GRAPH = 6
 POLAR_OPT_FWG = 7
 POLAR_STATIC_SCRATCH_BYTES = 256 << 20
 POLAR_STATIC_MAX_FRAMES = 16384
+POLAR_CONSTRUCT_MAX_MU = 64
+POLAR_CONSTRUCT_MAX_OUTPUTS = 65536
 
 # every symbol declared in include/polar.h
 EXPORTED = [
@@ -52,6 +54,7 @@ EXPORTED = [
     "polar_tune_save", "polar_tune_load", "polar_serve_open", "polar_serve_submit", "polar_serve_poll",
     "polar_serve_pending", "polar_serve_stats", "polar_serve_cancel", "polar_serve_close", "polar_serve",
     "polar_debug_lane_selftest", "polar_debug_phi_table", "polar_fer_generate_bsc", "polar_fer_workspace_bytes", "polar_fer_bsc",
+    "polar_construct_workspace_bytes", "polar_construct_degrade", "polar_frozen_from_pe",
 ]
 
 
@@ -162,6 +165,9 @@ def load():
         "polar_fer_generate_bsc": ([I, ctypes.c_double, I, P, ctypes.c_uint64, I64, I, P, P, P, P, P], I),
         "polar_fer_workspace_bytes": ([P, P], SZ),
         "polar_fer_bsc": ([P, P, P, SZ, P, P, P], I),
+        "polar_construct_workspace_bytes": ([I, I, I], SZ),
+        "polar_construct_degrade": ([I, P, I, I, P, SZ, P, P], I),
+        "polar_frozen_from_pe": ([I, P, I64, ctypes.c_double, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -212,6 +218,43 @@ def build_frozen_set(log2n: int, z0: float, n_frozen: int = -1, fer_bound: float
                                          mask.ctypes.data, None if r is None else r.ctypes.data,
                                          ctypes.addressof(nf)))
     return mask, int(nf.value), r
+
+
+def construct_workspace_bytes(log2n: int, mu: int, m0: int) -> int:
+    return int(load().polar_construct_workspace_bytes(int(log2n), int(mu), int(m0)))
+
+
+def construct_degrade(log2n: int, w0, mu: int, pe=None, workspace=None, stream=None):
+    """Error probabilities of the N synthetic channels by channel degradation
+    on the device.  w0: (m0, 2) array of output pairs (a, b) of the channel.
+    Returns pe, a float64 torch tensor of N values on the current device."""
+    import torch
+
+    w0 = np.ascontiguousarray(np.asarray(w0, np.float64).reshape(-1, 2))
+    m0 = w0.shape[0]
+    if pe is None:
+        pe = torch.empty(1 << log2n, dtype=torch.float64, device="cuda")
+    need = construct_workspace_bytes(log2n, mu, m0)
+    if need == 0:
+        _check(load().polar_construct_degrade(int(log2n), w0.ctypes.data, int(m0), int(mu), None, 0, None, None))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=pe.device)
+    _check(load().polar_construct_degrade(int(log2n), w0.ctypes.data, int(m0), int(mu), _ptr(workspace),
+                                          int(workspace.numel()), _ptr(pe), _stream_handle(stream)))
+    return pe
+
+
+def frozen_from_pe(log2n: int, pe, n_frozen: int = -1, fer_bound: float = 0.1):
+    """Host-side frozen set from per-channel error probabilities.  Returns
+    (mask words uint32, n_frozen)."""
+    pe = np.ascontiguousarray(np.asarray(pe, np.float64))
+    if pe.shape != (1 << log2n,):
+        raise ValueError("pe must hold N values")
+    mask = np.zeros(n_words(log2n), np.uint32)
+    nf = ctypes.c_int64(0)
+    _check(load().polar_frozen_from_pe(int(log2n), pe.ctypes.data, int(n_frozen), float(fer_bound),
+                                       mask.ctypes.data, ctypes.addressof(nf)))
+    return mask, int(nf.value)
 
 
 def encode(log2n: int, u, x=None, n_frames: Optional[int] = None, stream=None):
