@@ -500,6 +500,8 @@ def main(argv=None):
     ap.add_argument("--fwg", type=int, default=0,
                     help="frames per workgroup for frames of at most 2^cutover leaves (0 = library default)")
     ap.add_argument("--graph", type=int, default=0, help="replay the batch through a HIP graph")
+    ap.add_argument("--helpers", type=int, default=1,
+                    help="spare resident workgroups share the large sweeps of frames (when frames < workgroups)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-arena-gb", type=float, default=200.0,
@@ -548,6 +550,7 @@ def main(argv=None):
         ctx.set_option(lp.POLAR_OPT_CUTOVER, args.cutover)
     if args.fwg:
         ctx.set_option(lp.POLAR_OPT_FWG, args.fwg)
+    ctx.set_option(lp.POLAR_OPT_HELPERS, args.helpers)
     if args.graph:
         ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
     frames = lp.make_frames(items)
@@ -584,7 +587,7 @@ def main(argv=None):
                            bits_per_step=total_bits, info_bits_per_step=info_bits,
                            f_kind=["minsum", "boxplus", "minsum_q16", "phi_q16"][cfg["fkind"]],
                            prune=bool(args.prune),
-                           graph=bool(args.graph), decoder_source=source,
+                           graph=bool(args.graph), helpers=bool(args.helpers), decoder_source=source,
                            launch=ctx.query_launch(cfg["fkind"], max(it["log2n"] for it in items), n),
                            tuned=tuned),
                roofline=roof,

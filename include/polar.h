@@ -212,6 +212,14 @@ typedef struct polar_ctx polar_ctx;
                                    value, else enough to spread the small frames over
                                    every workgroup).  Frames above 2^cutover are decoded
                                    by a whole workgroup each.                          */
+#define POLAR_OPT_HELPERS 8     /* 0/1 (default 1): when a batch has fewer frames above
+                                   the cutover than workgroups that can be resident,
+                                   polar_sc_decode_batch (and the FER harness) launches
+                                   the spare ones as helpers that share each frame's
+                                   large HBM level sweeps (Section 4's internal
+                                   parallelism over the node's elements, across
+                                   compute units).  The serving loop never uses them
+                                   (its batches share the device).                     */
 #define POLAR_OPT_GRAPH 6       /* 0/1: polar_sc_decode_batch replays each distinct batch
                                    (same descriptors, options and workspace) through a
                                    cached HIP graph [descriptor copy, counter reset,

@@ -38,6 +38,7 @@ struct LaunchCfg {
     int fwg = 0;    // frames per workgroup for frames of at most 2^cutover leaves (0 = automatic)
     int prune = -1; // exact node shortcuts: 0 / 1, or -1 = the context's option
     int small_slots = 0;  // workgroups of the per-wavefront launch (computed, not tuned)
+    int helpers = 0;      // sweep helpers beside the frame workgroups (computed, not tuned)
 };
 
 // Frame sizes of one launch group: count per log2 N.
@@ -82,7 +83,8 @@ struct Plan {
     bool per_frame = false;
     int slots = 0;
     int64_t slot_bytes = 0;
-    size_t desc_off = 0, slot_off = 0, total = 0;
+    size_t desc_off = 0, box_off = 0, slot_off = 0, total = 0;
+    int boxes = 0;  // sweep mailboxes (frame workgroups of the largest launch with helpers)
 };
 
 struct GraphEntry {
@@ -105,6 +107,7 @@ struct polar_ctx {
     int max_slots = 0;  // 0 = automatic
     int fwg = 0;        // 0 = automatic
     int graph = 0;      // replay batches through cached HIP graphs
+    int helpers = 1;    // spare resident workgroups help with the sweeps of large frames
     unsigned long long* prof = nullptr;  // optional device timing counters
     polar_host::Stager stager;
     // resident workgroups per compute unit, per decoder variant and size
@@ -138,10 +141,12 @@ int occupancy(const polar_ctx* c, int cutover, int fk, bool dump, int waves, boo
 // be resident at once; frames of at most 2^cutover leaves are shared out
 // fwg per workgroup.
 LaunchCfg group_cfg(const polar_ctx* c, int fk, bool dump, const SizeHist& h, bool plain,
-                    const LaunchCfg* force = nullptr);
+                    const LaunchCfg* force = nullptr, bool helpers = true);
 // Slot bytes of one group under cfg: per workgroup (slots x largest frame)
 // or per frame (sum over the frames above the cutover).
 int64_t group_slot_bytes(const SizeHist& h, const LaunchCfg& cfg, bool per_frame, int64_t* per_wg);
+// per_frame: every frame gets its own slot (serving); it also keeps the
+// launches free of sweep helpers, so that batches can share the device.
 void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool plain, Plan& p,
                const LaunchCfg* force = nullptr, bool per_frame = false);
 // Enqueue the decode of a planned batch on stream s using workspace ws;

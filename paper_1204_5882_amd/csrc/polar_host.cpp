@@ -262,7 +262,8 @@ int occupancy(const polar_ctx* c, int cutover, int fk, bool dump, int waves, boo
     return occ;
 }
 
-LaunchCfg group_cfg(const polar_ctx* c, int fk, bool dump, const SizeHist& h, bool plain, const LaunchCfg* force) {
+LaunchCfg group_cfg(const polar_ctx* c, int fk, bool dump, const SizeHist& h, bool plain, const LaunchCfg* force,
+                    bool helpers) {
     LaunchCfg cfg;
     if (plain) {
         cfg.cutover = 12;
@@ -302,6 +303,9 @@ LaunchCfg group_cfg(const polar_ctx* c, int fk, bool dump, const SizeHist& h, bo
         }
     const int n_big = h.count - n_small;
     cfg.slots = std::max(1, std::min(cfg.slots, n_big));
+    // spare resident workgroups share the large frames' sweeps (not when the
+    // caller limited the workgroups with POLAR_OPT_MAX_SLOTS)
+    cfg.helpers = (helpers && c->helpers && n_big > 0 && c->max_slots <= 0) ? std::max(0, cap - cfg.slots) : 0;
     if (!n_small) {
         cfg.fwg = 1;
         cfg.small_slots = 1;
@@ -383,7 +387,7 @@ void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool
     p.slot_bytes = 0;
     int64_t frame_bytes = 0;  // per-frame slots: running offset
     for (auto& g : p.groups) {
-        g.cfg = group_cfg(c, g.fk, g.dump != 0, g.hist, plain, force);
+        g.cfg = group_cfg(c, g.fk, g.dump != 0, g.hist, plain, force, !p.per_frame);
         int64_t per_wg = 0;
         (void)group_slot_bytes(g.hist, g.cfg, p.per_frame, &per_wg);
         p.slots = std::max(p.slots, g.cfg.slots);
@@ -395,8 +399,12 @@ void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool
                     frame_bytes += polar_dev_slot_bytes(p.descs[(size_t)k].log2n, g.cfg.cutover);
                 }
     }
+    p.boxes = 0;
+    for (const auto& g : p.groups)
+        if (g.cfg.helpers > 0) p.boxes = std::max(p.boxes, g.cfg.slots);
     p.desc_off = kHeaderBytes;
-    p.slot_off = align256(p.desc_off + sizeof(FrameDesc) * (size_t)n_frames);
+    p.box_off = align256(p.desc_off + sizeof(FrameDesc) * (size_t)n_frames);
+    p.slot_off = align256(p.box_off + sizeof(SweepBox) * (size_t)p.boxes);
     p.total = p.slot_off + (p.per_frame ? (size_t)frame_bytes : (size_t)p.slots * (size_t)p.slot_bytes);
 }
 
@@ -416,6 +424,7 @@ int enqueue_launches(polar_ctx* c, const Plan& p, void* ws, hipStream_t s, bool 
     unsigned* counter = (unsigned*)base;
     const FrameDesc* dtab = (const FrameDesc*)(base + p.desc_off);
     uint8_t* slots = base + p.slot_off;
+    SweepBox* boxes = p.boxes > 0 ? reinterpret_cast<SweepBox*>(base + p.box_off) : nullptr;
     for (const auto& gr : p.groups) {
         DecodeLaunch a{};
         a.cutover = gr.cfg.cutover;
@@ -451,6 +460,8 @@ int enqueue_launches(polar_ctx* c, const Plan& p, void* ws, hipStream_t s, bool 
             a.n_frames = n_big;
             a.grid = gr.cfg.slots;
             a.small = 0;
+            a.helpers = boxes ? gr.cfg.helpers : 0;
+            a.boxes = boxes;
             hipError_t e = polar_dev_launch_decode(&a);
             if (e != hipSuccess) return hip_fail(e, "decode launch");
         }
@@ -681,6 +692,10 @@ extern "C" int polar_ctx_set_option(polar_ctx* c, int option, int64_t value) {
             if (value < 0 || value > 8) return fail(POLAR_E_INVAL, "frames per workgroup must be 0 .. 8");
             c->fwg = (int)value;
             return ok();
+        case POLAR_OPT_HELPERS:
+            if (value != 0 && value != 1) return fail(POLAR_E_INVAL, "helpers must be 0 or 1");
+            c->helpers = (int)value;
+            return ok();
         default:
             return fail(POLAR_E_INVAL, "unknown option %d", option);
     }
@@ -696,6 +711,7 @@ extern "C" int polar_ctx_get_option(polar_ctx* c, int option, int64_t* value) {
         case POLAR_OPT_TIMING: *value = (int64_t)(uintptr_t)c->prof; return ok();
         case POLAR_OPT_GRAPH: *value = c->graph; return ok();
         case POLAR_OPT_FWG: *value = c->fwg; return ok();
+        case POLAR_OPT_HELPERS: *value = c->helpers; return ok();
         default: return fail(POLAR_E_INVAL, "unknown option %d", option);
     }
 }

@@ -110,7 +110,7 @@ struct BatchSize {
         int64_t slots = 0;
         for (int k = 0; k < 8; ++k) {
             if (!h[k].count) continue;
-            const LaunchCfg cfg = group_cfg(c, k >> 1, (k & 1) != 0, h[k], false);
+            const LaunchCfg cfg = group_cfg(c, k >> 1, (k & 1) != 0, h[k], false, nullptr, false);
             slots += group_slot_bytes(h[k], cfg, true, nullptr);
         }
         return align256(256 + sizeof(FrameDesc) * (size_t)nf) + (size_t)slots;

@@ -21,6 +21,21 @@ struct FrameDesc {
 };
 static_assert(sizeof(FrameDesc) == 64, "descriptor layout");
 
+// Mailbox of one frame workgroup for cooperative level sweeps (128 bytes,
+// one per frame workgroup of a launch, zeroed before the launch).
+struct SweepBox {
+    unsigned long long claim;  // seq << 32 | partitions << 16 | next partition
+    uint32_t done;             // partitions finished by other workgroups for seq
+    int32_t op;                // 1: sweep2 with g first, 0: sweep2 with f first
+    const float* in;
+    const uint64_t* beta;
+    float* mid;
+    float* out;
+    int64_t half;
+    uint64_t pad[9];
+};
+static_assert(sizeof(SweepBox) == 128, "mailbox layout");
+
 // Everything one persistent decode launch needs.
 struct DecodeLaunch {
     int cutover;               // log2 of the register-resident subtree
@@ -39,6 +54,8 @@ struct DecodeLaunch {
     int small;                 // 1: every frame has at most 2^cutover leaves (per-wavefront kernel)
     int small_log2n;           // small: log2 N of the largest (first) frame
     int fwg;                   // small: frames per workgroup = its wavefronts
+    int helpers;               // large frames: workgroups beyond grid that only help with sweeps
+    SweepBox* boxes;           // large frames: grid mailboxes (zeroed by the launch), or null
     hipStream_t stream;
 };
 

@@ -1094,6 +1094,209 @@ __device__ __forceinline__ void combine_words(uint64_t* beta, int64_t words, int
     for (int64_t i = tid; i < words; i += nt) beta[i] ^= beta[i + words];
 }
 
+// ---------------------------------------------------------------------------
+// Cooperative level sweeps.  A launch may hold more resident workgroups than
+// it has frames: the extra workgroups, and those whose frames are done, help
+// the frames' workgroups with their large two-level sweeps over HBM.  A
+// frame's workgroup posts the sweep in its mailbox, split into partitions
+// (partition p runs the sweep as waves p W .. p W + W - 1 of a virtual
+// workgroup of P W waves); every workgroup, the poster included, claims
+// partitions by a compare-and-swap on the mailbox's claim word (sequence
+// number, partition count, next partition).  The poster waits only for
+// partitions that others have already claimed, so no workgroup ever waits
+// for one that has not started, and with no helper the poster runs every
+// partition itself.  Data crosses compute units (and their L2 caches)
+// through device-scope release fences before the post and before each
+// partition's completion count, and acquire fences after the claim and
+// after the wait.
+// ---------------------------------------------------------------------------
+// Optional timing: wave 0 accumulates, in s_memrealtime ticks (100 MHz), the
+// time spent in register-resident subtree decoding.
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+constexpr uint64_t HELP_IDLE_TICKS = 100000000ull;  // 1 s of the 100 MHz clock
+constexpr int COOP_MIN_ROWS = 512;  // rows of 256 outputs below which a sweep is not shared
+constexpr int COOP_MAX_PARTS = 64;
+
+__device__ __forceinline__ void fence_release_dev() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire_dev() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+__device__ __forceinline__ unsigned long long claim_load(SweepBox* b) {
+    return __hip_atomic_load(&b->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claims the next partition of the sweep with sequence number seq (seq = 0:
+// whatever sweep is open).  Returns the partition, or -1 when none is left.
+__device__ __forceinline__ int claim_part(SweepBox* b, uint32_t seq, int* parts_out) {
+    unsigned long long w = claim_load(b);
+    while (true) {
+        const uint32_t sq = (uint32_t)(w >> 32);
+        const int parts = (int)((w >> 16) & 0xffffu), next = (int)(w & 0xffffu);
+        if (sq == 0 || (seq != 0 && sq != seq) || next >= parts) return -1;
+        if (__hip_atomic_compare_exchange_strong(&b->claim, &w, w + 1ull, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+            *parts_out = parts;
+            return next;
+        }
+    }
+}
+
+template <int C, int FK>
+__device__ __forceinline__ void run_part(int op, const float* in, int64_t h, const uint64_t* beta, float* mid,
+                                         float* out, int part, int parts, int wave, int W) {
+    if (op) sweep2<C, FK, true>(in, h, beta, mid, out, part * W + wave, parts * W);
+    else sweep2<C, FK, false>(in, h, nullptr, mid, out, part * W + wave, parts * W);
+}
+
+// Per-workgroup state of the cooperative sweeps, kept in LDS and read
+// through volatile loads where used, so that it holds no registers across
+// the leaf decoder.
+struct CoopState {
+    SweepBox* box;    // this frame workgroup's mailbox, or null (no helpers)
+    SweepBox* boxes;  // the launch's mailboxes (one per frame workgroup), or null
+    int n_main;       // frame workgroups of the launch
+    uint32_t seq;     // sequence number of its last posted sweep
+    int cmd[3];       // claim broadcast: mailbox, partition, partitions
+};
+
+// Variants that take helpers.  The pruned cutover-12 min-sum variants (the
+// straight-line 64-leaf patterns) already use every register the leaf
+// decoder can have; the cooperative code tips them into spilling, so they
+// decode their frames alone.
+template <int C, int FK, bool PRUNE, bool DUMP>
+constexpr bool coop_variant() {
+    return !(C == 12 && PRUNE && !DUMP && (FK == 0 || FK == 2));
+}
+
+// sweep2 over the whole workgroup, shared with helpers when it is large and
+// the workgroup has a mailbox.  Ends with the workgroup synchronised and the
+// outputs visible to it.
+template <int C, int FK, bool G, bool COOP>
+__device__ __forceinline__ void coop_sweep2(bool shareable, CoopState* cs, const float* in, int64_t h,
+                                            const uint64_t* beta, float* mid, float* out, int wave, int W) {
+    const int64_t rows = (h >> 1) >> 8;
+    SweepBox* box = COOP && shareable ? *(SweepBox* volatile*)&cs->box : nullptr;
+    if (!COOP || box == nullptr || rows < COOP_MIN_ROWS) {
+        sweep2<C, FK, G>(in, h, beta, mid, out, wave, W);
+        __syncthreads();
+        return;
+    }
+    int parts = (int)(rows / (SWEEP_UNROLL * W));
+    parts = parts < COOP_MAX_PARTS ? parts : COOP_MAX_PARTS;
+    // everything this workgroup wrote (levels, partial sums) is read by others
+    fence_release_dev();
+    __syncthreads();
+    const uint32_t seq = *(volatile uint32_t*)&cs->seq + 1u;
+    int* s_part = &cs->cmd[0];
+    __syncthreads();  // every thread has read seq before thread 0 advances it
+    if (threadIdx.x == 0) {
+        cs->seq = seq;
+        box->op = G ? 1 : 0;
+        box->in = in;
+        box->beta = beta;
+        box->mid = mid;
+        box->out = out;
+        box->half = h;
+        __hip_atomic_store(&box->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&box->claim, ((unsigned long long)seq << 32) | ((unsigned long long)parts << 16),
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int own = 0;
+    while (true) {
+        if (threadIdx.x == 0) {
+            int pp = 0;
+            *s_part = claim_part(box, seq, &pp);
+        }
+        __syncthreads();
+        const int p = *s_part;
+        __syncthreads();
+        if (p < 0) break;
+        ++own;
+        run_part<C, FK>(G ? 1 : 0, in, h, beta, mid, out, p, parts, wave, W);
+    }
+    if (threadIdx.x == 0) {
+        // partitions claimed by other workgroups are running and end on their
+        // own; the bound (2^28 polls, seconds) only keeps a broken count
+        // from hanging the device
+        const uint32_t others = (uint32_t)(parts - own);
+        for (uint32_t it = 0; it < (1u << 28); ++it) {
+            if (__hip_atomic_load(&box->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= others) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    fence_acquire_dev();
+}
+
+// A workgroup without a frame: claims partitions of any open sweep of the
+// launch until every frame is done (frames_done reaches n_frames), or until
+// it has found nothing to do for a second (a helper that leaves only costs
+// speed: frame workgroups never wait for unclaimed partitions).
+
+template <int C, int FK>
+__device__ __forceinline__ void help_sweeps(SweepBox* boxes, int n_boxes, const unsigned* frames_done, int n_frames,
+                                            int* s_cmd) {
+    const int W = (int)(blockDim.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // each helper watches its own frame workgroup's mailbox and looks at all
+    // of them every 8th poll (the polls are device-scope loads)
+    const int home = (int)(blockIdx.x % (unsigned)n_boxes);
+    unsigned poll = 0;
+    uint64_t idle_since = now_ticks();
+    while (true) {
+        if (threadIdx.x == 0) {
+            s_cmd[0] = -1;
+            const int span = (poll & 7u) == 7u ? n_boxes : 1;
+            for (int k = 0; k < span; ++k) {
+                const int b = home + k < n_boxes ? home + k : home + k - n_boxes;
+                int parts = 0;
+                const int p = claim_part(boxes + b, 0u, &parts);
+                if (p >= 0) {
+                    s_cmd[0] = b;
+                    s_cmd[1] = p;
+                    s_cmd[2] = parts;
+                    break;
+                }
+            }
+            if (s_cmd[0] < 0) {
+                ++poll;
+                if (__hip_atomic_load(frames_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)n_frames ||
+                    now_ticks() - idle_since > HELP_IDLE_TICKS)
+                    s_cmd[0] = -2;
+                else
+                    __builtin_amdgcn_s_sleep(32);
+            } else {
+                idle_since = now_ticks();
+            }
+        }
+        __syncthreads();
+        const int b = __builtin_amdgcn_readfirstlane(s_cmd[0]);
+        const int p = __builtin_amdgcn_readfirstlane(s_cmd[1]);
+        const int parts = __builtin_amdgcn_readfirstlane(s_cmd[2]);
+        __syncthreads();
+        if (b == -2) break;
+        if (b < 0) continue;
+        fence_acquire_dev();
+        SweepBox* x = boxes + b;
+        const auto uptr = [](const void* q) {
+            const uint64_t v = (uint64_t)q;
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+            return ((uint64_t)hi << 32) | lo;
+        };
+        const int op = __builtin_amdgcn_readfirstlane(x->op);
+        const float* in = (const float*)uptr(x->in);
+        const uint64_t* beta = (const uint64_t*)uptr(x->beta);
+        float* mid = (float*)uptr(x->mid);
+        float* out = (float*)uptr(x->out);
+        const int64_t h = (int64_t)uptr((const void*)x->half);
+        run_part<C, FK>(op, in, h, beta, mid, out, p, parts, wave, W);
+        fence_release_dev();
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(&x->done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // Byte offsets inside one frame slot of the workspace.
 __host__ __device__ inline int64_t slot_level_offset(int log2n, int d) {
     // level d (1 <= d) holds N >> d floats; levels are packed from d = 1
@@ -1101,15 +1304,12 @@ __host__ __device__ inline int64_t slot_level_offset(int log2n, int d) {
     return (n - (n >> (d - 1))) * 4;
 }
 
-// Optional timing: wave 0 accumulates, in s_memrealtime ticks (100 MHz), the
-// time spent in register-resident subtree decoding.
-__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
 // A frame of 2^n > 2^C leaves, decoded by the whole workgroup: sweeps over
 // the levels above the cutover, one wavefront per subtree.
 template <int C, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot, float* lds, float* tier,
-                                             uint32_t* words, uint64_t* lbeta, uint64_t& sub_ticks) {
+                                             uint32_t* words, uint64_t* lbeta, uint64_t& sub_ticks, CoopState* cs) {
     const int W = (int)(blockDim.x >> 6);  // wavefronts in the workgroup
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps sweep offsets scalar
@@ -1156,19 +1356,24 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
             // are the last one or two subtrees', read from their LDS copy)
             if (t == 0) {
                 sweep_g<C, FK>(level(dp), half, lbeta, lds, wave, W);
+                __syncthreads();
             } else if (t == 1) {
                 sweep2<C, FK, true>(level(dp), half, lbeta, level(D - t), lds, wave, W);
+                __syncthreads();
             } else {
-                sweep2<C, FK, true>(level(dp), half, bl, level(D - t), level(D - t + 1), wave, W);
+                // both outputs in HBM (t >= 4) can be shared with helpers
+                coop_sweep2<C, FK, true, coop_variant<C, FK, PRUNE, DUMP>()>(t >= 4, cs, level(dp), half, bl,
+                                                                             level(D - t), level(D - t + 1), wave, W);
             }
-            __syncthreads();
         }
         // rest of the f chain down to the cutover depth (the cutover node goes
         // to LDS), two levels per pass
         int d = (s == 0) ? 1 : D - t + 2;
         for (; d + 1 <= D; d += 2) {
-            sweep2<C, FK, false>(level(d - 1), N >> d, nullptr, level(d), d + 1 == D ? lds : level(d + 1), wave, W);
-            __syncthreads();
+            // outputs at depths d, d + 1 <= D - 3 are in HBM: shareable
+            coop_sweep2<C, FK, false, coop_variant<C, FK, PRUNE, DUMP>()>(d + 1 <= D - 3, cs, level(d - 1), N >> d,
+                                                                          nullptr, level(d),
+                                                                          d + 1 == D ? lds : level(d + 1), wave, W);
         }
         if (d == D) {
             sweep_f<FK>(level(d - 1), N >> d, lds, wave, W);
@@ -1255,17 +1460,29 @@ template <int C, int FK, bool PRUNE, bool DUMP, int MAXW>
 __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __restrict__ descs, int n_frames,
                                                        unsigned* __restrict__ counter, uint8_t* slots,
                                                        int64_t slot_bytes, unsigned long long* prof,
-                                                       uint32_t* done) {
+                                                       uint32_t* done, SweepBox* boxes, int n_main) {
     __shared__ float lds_all[LDS_FLOATS<C>];
     __shared__ int s_frame;
+    __shared__ CoopState s_coop;
     __shared__ uint32_t s_words[2][2 << (C - 5)];  // staged mask and value words of the next subtree
     __shared__ uint64_t s_beta[2][64];  // partial sums of the last two subtrees (slot s & 1)
     constexpr int LDS_SUB = LDS_FLOATS<C> - TIER_FLOATS<C>;
     float* lds = lds_all;
     float* tier = lds_all + LDS_SUB;  // LLR levels of sizes 2^(C+1) and 2^(C+2)
+    // workgroups 0 .. n_main-1 decode frames (then help); the rest only help.
+    // The cooperative state goes to LDS at once, so that none of it holds
+    // registers across the frame loop.
+    const bool main_wg = (int)blockIdx.x < n_main;
     uint8_t* wg_slot = slots + (int64_t)blockIdx.x * slot_bytes;
-    if constexpr (FK == 3) phi_table_init();  // the barrier below orders it
-    while (true) {
+    if (threadIdx.x == 0) {
+        s_coop.box = boxes != nullptr && main_wg ? boxes + blockIdx.x : nullptr;
+        s_coop.boxes = boxes;
+        s_coop.n_main = n_main;
+        s_coop.seq = 0;
+    }
+    if constexpr (FK == 3) phi_table_init();
+    __syncthreads();
+    while (main_wg) {
         if (threadIdx.x == 0) s_frame = (int)atomicAdd(counter, 1u);
         __syncthreads();
         const int f = s_frame;
@@ -1276,14 +1493,21 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __rest
         uint64_t sub_ticks = 0;
         const uint64_t t0 = prof ? now_ticks() : 0;
         decode_frame<C, FK, PRUNE, DUMP>(fd, fd.slot ? fd.slot : wg_slot, lds, tier, &s_words[0][0], &s_beta[0][0],
-                                         sub_ticks);
+                                         sub_ticks, &s_coop);
         __syncthreads();
         if (threadIdx.x < 64) signal_done(fd, done);
+        if (threadIdx.x == 0 && *(SweepBox* volatile*)&s_coop.box != nullptr)
+            __hip_atomic_fetch_add(counter + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // frames done
         if (prof && threadIdx.x == 0) {
             atomicAdd(prof + 0, (unsigned long long)sub_ticks);
             atomicAdd(prof + 1, (unsigned long long)(now_ticks() - t0));
             atomicAdd(prof + 2, 1ull);
         }
+    }
+    if constexpr (coop_variant<C, FK, PRUNE, DUMP>()) {
+        SweepBox* const all = *(SweepBox* volatile*)&s_coop.boxes;
+        const int nm = *(volatile int*)&s_coop.n_main;
+        if (all != nullptr && (int)gridDim.x > nm) help_sweeps<C, FK>(all, nm, counter + 32, n_frames, &s_coop.cmd[0]);
     }
 }
 
@@ -1320,8 +1544,15 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode_small(const FrameDesc* 
 
 // Work-counter reset (a kernel rather than a memset, so that the launch can
 // be captured into a graph).
-static __global__ void k_reset_counter(unsigned* counter) {
-    if (threadIdx.x == 0) counter[0] = 0u;
+static __global__ void k_reset_counter(unsigned* counter, SweepBox* boxes, int n_boxes) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counter[0] = 0u;   // work counter
+        counter[32] = 0u;  // frames done (cooperative sweeps)
+    }
+    uint64_t* w = reinterpret_cast<uint64_t*>(boxes);
+    const int64_t words = (int64_t)n_boxes * (int64_t)(sizeof(SweepBox) / 8);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = 0ull;
 }
 
 // Every variant fits the register budget of 8 wavefronts per workgroup.
@@ -1332,7 +1563,12 @@ hipError_t launch_decode(const DecodeLaunch& a) {
     constexpr int MAXW = MAX_WAVES;
     if (a.waves < 1 || a.waves > MAXW) return hipErrorInvalidValue;
     const int waves = a.waves;
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, a.stream, a.counter);
+    // (without helpers a frame's workgroup would run its shared sweeps as
+    // partitions one after another: no mailboxes then)
+    SweepBox* boxes = a.small || a.helpers <= 0 || !coop_variant<C, FK, PRUNE, DUMP>() ? nullptr : a.boxes;
+    const int n_boxes = boxes ? a.grid : 0;
+    hipLaunchKernelGGL(k_reset_counter, dim3(n_boxes > 16 ? (n_boxes + 15) / 16 : 1), dim3(256), 0, a.stream,
+                       a.counter, boxes, n_boxes);
     if (a.small) {
         // every frame of the launch has at most 2^C leaves, the first one the
         // most; one wavefront per frame in flight, each with its LDS region
@@ -1349,8 +1585,11 @@ hipError_t launch_decode(const DecodeLaunch& a) {
         hipLaunchKernelGGL(kern, dim3(a.grid), dim3(a.fwg * 64), smem, a.stream, a.descs, a.n_frames, a.counter,
                            a.prof, a.done, region);
     } else {
-        hipLaunchKernelGGL((k_sc_decode<C, FK, PRUNE, DUMP, MAXW>), dim3(a.grid), dim3(waves * 64), 0, a.stream,
-                           a.descs, a.n_frames, a.counter, a.slots, a.slot_bytes, a.prof, a.done);
+        if (a.helpers < 0 || (a.helpers > 0 && a.boxes == nullptr)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_sc_decode<C, FK, PRUNE, DUMP, MAXW>), dim3(a.grid + (boxes ? a.helpers : 0)),
+                           dim3(waves * 64), 0,
+                           a.stream, a.descs, a.n_frames, a.counter, a.slots, a.slot_bytes, a.prof, a.done, boxes,
+                           a.grid);
     }
     return hipGetLastError();
 }

@@ -40,6 +40,7 @@ POLAR_OPT_MAX_SLOTS = 4
 POLAR_OPT_TIMING = 5
 POLAR_OPT_GRAPH = 6
 POLAR_OPT_FWG = 7
+POLAR_OPT_HELPERS = 8
 POLAR_STATIC_SCRATCH_BYTES = 256 << 20
 POLAR_STATIC_MAX_FRAMES = 16384
 POLAR_CONSTRUCT_MAX_MU = 64
