@@ -1115,7 +1115,7 @@ __device__ __forceinline__ void combine_words(uint64_t* beta, int64_t words, int
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
 constexpr uint64_t HELP_IDLE_TICKS = 100000000ull;  // 1 s of the 100 MHz clock
-constexpr int COOP_MIN_ROWS = 512;  // rows of 256 outputs below which a sweep is not shared
+constexpr int COOP_MIN_ROWS = 128;  // rows of 256 outputs below which a sweep is not shared
 constexpr int COOP_MAX_PARTS = 64;
 
 __device__ __forceinline__ void fence_release_dev() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
