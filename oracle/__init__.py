@@ -16,6 +16,12 @@ Parity status of each function (what pins it is listed in the tests):
   sc_decode minsum  pinned: naive per-bit SC (N <= 64), closed forms at scale
   sc_decode boxplus pinned: brute-force likelihood SC (N <= 16), mpmath f
   phi_table         pinned: 60-digit mpmath phi, involution, monotonicity
+  scl_decode        pinned: L = 1 equals sc_decode; a per-bit list decoder
+                    built on naive.py's re-encoding SC (N <= 32); the final
+                    metric equals the codeword's correlation discrepancy
+                    sum |L_j| [x_j != hard_j] (max-log ML metric) at any N;
+                    with L >= 2^K it returns a discrepancy minimiser (brute
+                    force over all codewords)
   sc_decode_fixed   pinned: naive per-bit SC in the same integer arithmetic
                     (N <= 64), FP32 min-sum equality without saturation,
                     saturation at the int16 bounds, phi-table LLRs within the
@@ -78,6 +84,8 @@ def _load():
     lib.oracle_sc_decode_fixed.restype = ctypes.c_int
     lib.oracle_f_fixed.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int]
     lib.oracle_f_fixed.restype = ctypes.c_int32
+    lib.oracle_scl_decode.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+    lib.oracle_scl_decode.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -223,6 +231,25 @@ def sc_decode_fixed(llr_q, frozen, fval, kind: int = FIXED_MINSUM, teacher=None,
 def f_fixed(kind: int, a: int, b: int, table=None) -> int:
     tab = np.ascontiguousarray(table if table is not None else phi_table(), np.int32)
     return int(_load().oracle_f_fixed(int(kind), int(a), int(b), _ptr(tab), int(tab.size)))
+
+
+def scl_decode(llr, frozen, fval, list_size: int):
+    """SC list decoding with FP32 min-sum updates and the LLR path metric
+    (Section 4 names list decoders as the improvement of SC).  Returns
+    (u_hat of the path of least metric, that metric as float32)."""
+    llr = np.ascontiguousarray(np.asarray(llr, dtype=np.float32))
+    n = llr.shape[0]
+    log2n = n.bit_length() - 1
+    if (1 << log2n) != n:
+        raise ValueError("N must be a power of two")
+    frozen = _bits(frozen, n)
+    fval = _bits(fval, n)
+    u = np.empty(n, np.uint8)
+    pm = ctypes.c_float(0.0)
+    if _load().oracle_scl_decode(log2n, int(list_size), _ptr(llr), _ptr(frozen), _ptr(fval), _ptr(u),
+                                 ctypes.addressof(pm)) != 0:
+        raise ValueError("oracle_scl_decode failed")
+    return u, np.float32(pm.value)
 
 
 def f_minsum(a: float, b: float) -> float:

@@ -169,3 +169,32 @@ def naive_sc_fixed(llr_q, frozen, fval, kind, table, teacher=None):
         u.append(ui)
         used.append(int(teacher[i]) if teacher is not None else ui)
     return np.array(u, np.uint8), np.array(leaves, np.int64)
+
+
+def naive_scl(llr, frozen, fval, list_size):
+    """Per-bit SC list decoding with FP32 min-sum leaf LLRs computed by
+    _leaf_llr on each path's own decisions (N <= 32): at an information leaf
+    every path offers both bits, metric PM + |lambda| for the bit against
+    the hard decision [lambda < 0]; candidates ordered by (metric, path,
+    bit), the first list_size kept in that order; frozen leaves add |lambda|
+    when the frozen value disagrees.  Returns (u_hat of the least metric,
+    ties to the lower path, its metric)."""
+    llr = [F32(v) for v in np.asarray(llr, dtype=np.float32)]
+    n = len(llr)
+    if n > 32:
+        raise ValueError("naive_scl is for N <= 32")
+    paths = [([], F32(0.0))]
+    for i in range(n):
+        lam = [_leaf_llr(llr, i, u) for u, _ in paths]
+        if frozen[i]:
+            b = int(fval[i])
+            paths = [(u + [b], F32(pm + abs(l)) if b != int(l < 0) else pm) for (u, pm), l in zip(paths, lam)]
+            continue
+        cand = []
+        for p, ((u, pm), l) in enumerate(zip(paths, lam)):
+            for b in (0, 1):
+                cand.append((F32(pm + abs(l)) if b != int(l < 0) else pm, p, b))
+        cand.sort(key=lambda c: (float(c[0]), c[1], c[2]))
+        paths = [(paths[p][0] + [b], pm) for pm, p, b in cand[:list_size]]
+    best = min(range(len(paths)), key=lambda k: (float(paths[k][1]), k))
+    return np.array(paths[best][0], np.uint8), paths[best][1]

@@ -446,6 +446,141 @@ int oracle_sc_decode_fixed(int log2n, int kind, const int32_t* llr, const uint8_
 }
 
 /* Scalar updates exported for the tests that pin them. */
+/* ------------------------------------------------------------------------ */
+/* SC list decoding (the list decoders the paper names as an improvement of */
+/* SC in Section 4; Tal and Vardy, with the LLR form of the path metric of  */
+/* Balatsoukas-Stimming, Bastani Parizi and Burg).  FP32 min-sum f and g as */
+/* in oracle_sc_decode.  Up to L paths are kept; each carries its decided   */
+/* bits and a path metric PM (FP32, starts at 0).  At leaf i every path     */
+/* computes its leaf LLR lambda by SC on its own decisions, and:            */
+/*   frozen i:  u = frozen value, PM += |lambda| if u != [lambda < 0]        */
+/*   info i:    each path p offers (u = b, PM_p + (b != [lambda < 0] ?       */
+/*              |lambda| : 0)) for b = 0, 1; the candidates are ordered by   */
+/*              (metric, p, b) and the first min(L, count) become the new    */
+/*              paths, in that order                                         */
+/* The output is the path of least PM, ties to the lower path index; its    */
+/* metric goes to *pm_out.                                                   */
+/* Per path the state is the LLRs of the current node at every depth and    */
+/* the decided bits; the partial sums a g needs are the left sibling's      */
+/* decisions re-encoded.  A surviving candidate copies its parent's state.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    float* a;    /* depth d (1..n) at a + (N - (N >> (d - 1))), N >> d floats */
+    uint8_t* u;  /* decided bits 0 .. i-1 */
+    float pm;
+} scl_path;
+
+static float* scl_level(const scl_path* p, int64_t n, int d) { return p->a + (n - (n >> (d - 1))); }
+
+/* LLR of leaf i for one path: the nodes that change between leaves i-1 and  */
+/* i are recomputed, from depth n - t (t = trailing zeros of i) down.        */
+static float scl_leaf(scl_path* p, const float* llr, int log2n, int64_t i, uint8_t* beta) {
+    const int64_t n = (int64_t)1 << log2n;
+    int top = 1;
+    if (i > 0) {
+        int t = 0;
+        while (((i >> t) & 1) == 0) ++t;
+        top = log2n - t; /* depth of the new right child */
+        const int64_t m = n >> (top - 1), h = m / 2; /* parent size */
+        const float* par = top == 1 ? llr : scl_level(p, n, top - 1);
+        float* out = scl_level(p, n, top);
+        /* left sibling: leaves [i - h, i), re-encoded */
+        encode_rec(p->u + (i - h), beta, h);
+        for (int64_t j = 0; j < h; ++j) out[j] = g_f32(par[j], par[j + h], beta[j]);
+        ++top;
+    }
+    for (int d = top; d <= log2n; ++d) {
+        const int64_t m = n >> (d - 1), h = m / 2;
+        const float* par = d == 1 ? llr : scl_level(p, n, d - 1);
+        float* out = scl_level(p, n, d);
+        for (int64_t j = 0; j < h; ++j) out[j] = f_minsum(par[j], par[j + h]);
+    }
+    return log2n == 0 ? llr[0] : scl_level(p, n, log2n)[0];
+}
+
+typedef struct {
+    float pm;
+    int parent, bit;
+} scl_cand;
+
+static int scl_before(const scl_cand* x, const scl_cand* y) {
+    if (x->pm != y->pm) return x->pm < y->pm;
+    if (x->parent != y->parent) return x->parent < y->parent;
+    return x->bit < y->bit;
+}
+
+int oracle_scl_decode(int log2n, int list, const float* llr, const uint8_t* frozen, const uint8_t* fval,
+                      uint8_t* u_hat, float* pm_out) {
+    if (log2n < 0 || log2n > 20 || list < 1 || list > 64 || !llr || !frozen || !fval || !u_hat) return -1;
+    const int64_t n = (int64_t)1 << log2n;
+    scl_path* cur = (scl_path*)calloc((size_t)list, sizeof(scl_path));
+    scl_path* nxt = (scl_path*)calloc((size_t)list, sizeof(scl_path));
+    for (int k = 0; k < list; ++k) {
+        cur[k].a = (float*)calloc((size_t)n, sizeof(float));
+        cur[k].u = (uint8_t*)calloc((size_t)n, 1);
+        nxt[k].a = (float*)calloc((size_t)n, sizeof(float));
+        nxt[k].u = (uint8_t*)calloc((size_t)n, 1);
+    }
+    uint8_t* beta = (uint8_t*)malloc((size_t)n);
+    float* lam = (float*)malloc(sizeof(float) * (size_t)list);
+    scl_cand* cand = (scl_cand*)malloc(sizeof(scl_cand) * 2 * (size_t)list);
+    int active = 1;
+    cur[0].pm = 0.0f;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < active; ++k) lam[k] = scl_leaf(&cur[k], llr, log2n, i, beta);
+        if (frozen[i]) {
+            const int b = fval[i];
+            for (int k = 0; k < active; ++k) {
+                if (b != (lam[k] < 0.0f)) cur[k].pm = cur[k].pm + fabsf(lam[k]);
+                cur[k].u[i] = (uint8_t)b;
+            }
+            continue;
+        }
+        int nc = 0;
+        for (int k = 0; k < active; ++k)
+            for (int b = 0; b < 2; ++b) {
+                scl_cand c = {cur[k].pm, k, b};
+                if (b != (lam[k] < 0.0f)) c.pm = cur[k].pm + fabsf(lam[k]);
+                /* insertion into the ordered list */
+                int at = nc++;
+                while (at > 0 && scl_before(&c, &cand[at - 1])) {
+                    cand[at] = cand[at - 1];
+                    --at;
+                }
+                cand[at] = c;
+            }
+        const int keep = nc < list ? nc : list;
+        for (int k = 0; k < keep; ++k) {
+            const scl_path* par = &cur[cand[k].parent];
+            memcpy(nxt[k].a, par->a, sizeof(float) * (size_t)n);
+            memcpy(nxt[k].u, par->u, (size_t)i);
+            nxt[k].u[i] = (uint8_t)cand[k].bit;
+            nxt[k].pm = cand[k].pm;
+        }
+        scl_path* t = cur;
+        cur = nxt;
+        nxt = t;
+        active = keep;
+    }
+    int best = 0;
+    for (int k = 1; k < active; ++k)
+        if (cur[k].pm < cur[best].pm) best = k;
+    memcpy(u_hat, cur[best].u, (size_t)n);
+    if (pm_out) *pm_out = cur[best].pm;
+    for (int k = 0; k < list; ++k) {
+        free(cur[k].a);
+        free(cur[k].u);
+        free(nxt[k].a);
+        free(nxt[k].u);
+    }
+    free(cur);
+    free(nxt);
+    free(beta);
+    free(lam);
+    free(cand);
+    return 0;
+}
+
 float oracle_f_minsum(float a, float b) { return f_minsum(a, b); }
 float oracle_g_f32(float a, float b, int u) { return g_f32(a, b, u); }
 double oracle_f_boxplus(double a, double b) { return f_boxplus(a, b); }
