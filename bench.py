@@ -467,6 +467,52 @@ def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1,
                 points=out, note="the paper's frozen sets come from density evolution [MT09]")
 
 
+def scl_leg(lp, torch, dev, log2n=10, p=0.05, k_info=563, n_frames=4096, lists=(1, 2, 4, 8, 16), seed=4242):
+    """SC list decoding on the device: frame error rate and decoding rate per
+    list size on synthetic BSC frames (the harness's generator), one code
+    (Bhattacharyya-ranked, K information bits); frames in error counted on
+    the host against the transmitted u.  The rate is frames x N over the
+    wall time of one call on prepared descriptors."""
+    import math
+
+    n = 1 << log2n
+    words, _, _ = lp.build_frozen_set(log2n, synth.bsc_z0(p), n - k_info, 0.1)
+    mdev = torch.from_numpy(words.view(np.int32).copy()).to(dev)
+    u, vals, llr = lp.fer_generate_bsc(log2n, p, mdev, seed, 0, n_frames)
+    w = lp.n_words(log2n)
+    uhat = torch.empty((n_frames, w), dtype=torch.int32, device=dev)
+    items = [dict(log2n=log2n, f_kind=0, llr=llr[k], frozen_mask=mdev, frozen_vals=vals[k], u_hat=uhat[k],
+                  leaf_llr=None) for k in range(n_frames)]
+    ctx = lp.Ctx(0)
+    cap = 1.0 + p * math.log2(p) + (1.0 - p) * math.log2(1.0 - p)
+    frames = lp.make_frames(items)
+    rows = []
+    for L in lists:
+        if (L << log2n) > lp.POLAR_SCL_MAX_NL:
+            continue
+        ctx.scl_decode(items, L)  # sizes the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.scl_decode_frames(frames, n_frames, L)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fe = int((uhat != u).any(dim=1).sum().item())
+        rows.append(dict(list_size=L, fer=round(fe / n_frames, 4), frame_errors=fe,
+                         Mbit_s=round(n_frames * n / wall / 1e6, 1)))
+    # the SC batch decoder on the same frames
+    ctx.decode(items)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.decode(items)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fe = int((uhat != u).any(dim=1).sum().item())
+    ctx.close()
+    return dict(code=f"N=2^{log2n}, K={k_info} (rate {k_info / n:.3f}, beta {k_info / n / cap:.3f}), BSC p={p}, "
+                     "Bhattacharyya-ranked frozen set, FP32 min-sum", frames=n_frames, per_list=rows,
+                sc_batch_decoder=dict(fer=round(fe / n_frames, 4), Mbit_s=round(n_frames * n / wall / 1e6, 1)))
+
+
 def copy_bandwidth(torch, dev, mib=1024):
     """Device-to-device copy of mib MiB timed with events: bytes read + written / time."""
     src = torch.ones((mib << 20) // 4, dtype=torch.float32, device=dev)
@@ -509,6 +555,7 @@ def main(argv=None):
     ap.add_argument("--tune", type=int, default=-1,
                     help="autotune the launch on the workload first (default: on for the mixed workload)")
     ap.add_argument("--no-fer", action="store_true", help="skip the FER / efficiency leg")
+    ap.add_argument("--no-scl", action="store_true", help="skip the SC list decoding leg")
     ap.add_argument("--per-frame-frames", type=int, default=8,
                     help="frames timed with the per-frame whole-GPU decoder (one batched call per frame)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -644,6 +691,9 @@ def main(argv=None):
                                 note="the batched decoder given one frame per call, serial on one stream")
         out["speedup_vs_per_frame"] = round(value / (pbits / pw / 1e6), 1)
 
+    if not args.no_scl:
+        print("[bench] SC list decoding leg", flush=True)
+        out["scl"] = scl_leg(lp, torch, dev)
     if not args.no_fer:
         print("[bench] FER / efficiency leg", file=sys.stderr, flush=True)
         out["fer"] = fer_leg(lp, torch, dev)

@@ -62,6 +62,10 @@ extern "C" {
 
 #define POLAR_MAX_LOG2N 24
 
+/* List decoding: paths per frame, and the largest N x paths (state on chip). */
+#define POLAR_SCL_MAX_LIST 16
+#define POLAR_SCL_MAX_NL 16384
+
 /* Degrading construction: outputs kept per channel, and outputs of the
    channel it starts from. */
 #define POLAR_CONSTRUCT_MAX_MU 64
@@ -445,6 +449,33 @@ int polar_fer_generate_bsc(int log2n, double p, int fixed_point, const uint32_t*
 size_t polar_fer_workspace_bytes(const polar_ctx* ctx, const polar_fer_cfg* cfg);
 int polar_fer_bsc(polar_ctx* ctx, const polar_fer_cfg* cfg, void* workspace, size_t ws_bytes,
                   uint32_t* bit_errors, polar_fer_result* out, void* stream);
+
+/*
+ * SC list decoding (Section 4 names list decoders as the improvement over
+ * SC).  Each frame keeps up to list_size paths; f and g are the FP32 min-sum
+ * updates of POLAR_F_MINSUM, and each path carries the LLR path metric:
+ *   frozen leaf:  u = frozen value; PM += |lambda| if u != [lambda < 0]
+ *   info leaf:    path p offers u = b, b = 0, 1, with PM_p + |lambda| when
+ *                 b != [lambda < 0] (else PM_p); candidates ordered by
+ *                 (metric, p, b), the first min(list_size, count) are the
+ *                 new paths in that order
+ * u_hat receives the path of least metric (ties to the lower path).  With
+ * min-sum updates the metric of a complete path equals the correlation
+ * discrepancy sum_j |L_j| [x_j != (L_j < 0)] of its codeword, so with
+ * list_size >= 2^K the result is a max-log maximum-likelihood codeword.
+ *
+ *   frames       host array as for polar_sc_decode_batch; f_kind must be
+ *                POLAR_F_MINSUM, leaf_llr NULL, and N x list_size <=
+ *                POLAR_SCL_MAX_NL (every path's state is on chip)
+ *   list_size    1 .. POLAR_SCL_MAX_LIST (1 is SC)
+ *   path_metric  device, n_frames floats (the chosen path's metric), or NULL
+ * Uses the context's workspace for the descriptor table
+ * (polar_scl_workspace_bytes).  Asynchronous on stream.  Errors:
+ * POLAR_E_INVAL, POLAR_E_NOMEM (workspace), POLAR_E_DEVICE.
+ */
+size_t polar_scl_workspace_bytes(int n_frames);
+int polar_scl_decode_batch(polar_ctx* ctx, const polar_frame* frames, int n_frames, int list_size,
+                           float* path_metric, void* stream);
 
 /*
  * Diagnostics: exercises the cross-lane moves (DPP row shifts, permlane

@@ -39,7 +39,7 @@ COMMON = [
 ]
 
 SOURCES = ["sc_device.hip", "polar_host.cpp", "polar_tune.cpp", "polar_serve.cpp", "polar_static.hip",
-           "polar_fer.hip", "polar_construct.hip"] + sorted(
+           "polar_fer.hip", "polar_construct.hip", "polar_scl.hip"] + sorted(
     os.path.relpath(f, CSRC) for f in glob.glob(os.path.join(CSRC, "variants", "*.hip")))
 
 # Device code runs with the IEEE mode bit off: min/max then need no NaN

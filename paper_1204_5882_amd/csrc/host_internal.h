@@ -112,7 +112,7 @@ struct polar_ctx {
     polar_host::Stager stager;
     // resident workgroups per compute unit, per decoder variant and size
     // (fixed size, filled on first use: lookups never allocate)
-    mutable std::vector<int> occ_cache = std::vector<int>(5 * 2 * 2 * 2 * 26 * 8, 0);
+    mutable std::vector<int> occ_cache = std::vector<int>(5 * 4 * 2 * 2 * 26 * 8, 0);
     // autotuned launch configurations, key (f_kind, log2n of the largest frame)
     std::map<std::pair<int, int>, polar_host::LaunchCfg> tuned;
     // allocation-free decoding (polar_sc_decode_batch_static): host tables

@@ -249,8 +249,8 @@ int validate_frames(const polar_frame* frames, int n_frames) {
 }
 
 int occupancy(const polar_ctx* c, int cutover, int fk, bool dump, int waves, bool prune, int small_log2n) {
-    // cache slot: cutover 8..12, f_kind, dump, prune, small_log2n -1..24, waves 1..8
-    const int key = (((((cutover - 8) * 2 + fk) * 2 + (dump ? 1 : 0)) * 2 + (prune ? 1 : 0)) * 26 + small_log2n + 1) *
+    // cache slot: cutover 8..12, f_kind 0..3, dump, prune, small_log2n -1..24, waves 1..8
+    const int key = (((((cutover - 8) * 4 + fk) * 2 + (dump ? 1 : 0)) * 2 + (prune ? 1 : 0)) * 26 + small_log2n + 1) *
                         8 + (waves - 1);
     const bool cacheable = cutover >= 8 && cutover <= 12 && waves >= 1 && waves <= 8 && small_log2n >= -1 &&
                            small_log2n <= POLAR_MAX_LOG2N && key >= 0 && key < (int)c->occ_cache.size();

@@ -44,6 +44,8 @@ POLAR_OPT_HELPERS = 8
 POLAR_STATIC_SCRATCH_BYTES = 256 << 20
 POLAR_STATIC_MAX_FRAMES = 16384
 POLAR_CONSTRUCT_MAX_MU = 64
+POLAR_SCL_MAX_LIST = 16
+POLAR_SCL_MAX_NL = 16384
 POLAR_CONSTRUCT_MAX_OUTPUTS = 65536
 
 # every symbol declared in include/polar.h
@@ -56,6 +58,7 @@ EXPORTED = [
     "polar_serve_pending", "polar_serve_stats", "polar_serve_cancel", "polar_serve_close", "polar_serve",
     "polar_debug_lane_selftest", "polar_debug_phi_table", "polar_fer_generate_bsc", "polar_fer_workspace_bytes", "polar_fer_bsc",
     "polar_construct_workspace_bytes", "polar_construct_degrade", "polar_frozen_from_pe",
+    "polar_scl_workspace_bytes", "polar_scl_decode_batch",
 ]
 
 
@@ -169,6 +172,8 @@ def load():
         "polar_construct_workspace_bytes": ([I, I, I], SZ),
         "polar_construct_degrade": ([I, P, I, I, P, SZ, P, P], I),
         "polar_frozen_from_pe": ([I, P, I64, ctypes.c_double, P, P], I),
+        "polar_scl_workspace_bytes": ([I], SZ),
+        "polar_scl_decode_batch": ([P, P, I, I, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -374,6 +379,25 @@ class Ctx:
         if need > have:
             # torch's caching allocator returns 512-byte aligned blocks
             self.set_workspace(torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}"))
+
+    def scl_decode(self, items: Iterable[dict], list_size: int, path_metric=None, stream=None):
+        """SC list decoding of min-sum frames (polar_scl_decode_batch); the
+        chosen path's metric goes to path_metric (device float32) if given."""
+        import torch
+
+        items = list(items)
+        frames = make_frames(items)
+        need = int(self._lib.polar_scl_workspace_bytes(len(items)))
+        have = 0 if self.workspace is None else self.workspace.numel()
+        if need > have:
+            self.set_workspace(torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}"))
+        self.scl_decode_frames(frames, len(items), list_size, path_metric, stream)
+
+    def scl_decode_frames(self, frames: ctypes.Array, n: int, list_size: int, path_metric=None, stream=None):
+        """polar_scl_decode_batch on a prepared frame array (make_frames); the
+        workspace must already hold the descriptor table."""
+        _check(self._lib.polar_scl_decode_batch(self._h, frames, int(n), int(list_size), _ptr(path_metric),
+                                                _stream_handle(stream)))
 
     def decode_batch(self, frames: ctypes.Array, n: int, stream=None):
         _check(self._lib.polar_sc_decode_batch(self._h, frames, int(n), _stream_handle(stream)))
