@@ -47,13 +47,13 @@ __device__ __forceinline__ float lane_readf(float x, int l) {
 __device__ __forceinline__ int depth_off(int n_leaves, int d) { return n_leaves - (n_leaves >> (d - 1)); }
 
 // LDS of one frame, in this order: LLRs [list][N] floats, frozen mask and
-// value words [2][max(1, N/32)], slot table [list] ints, decided bits
-// [list][N] bytes, partial-sum scratch [list][max(1, N/2)] bytes.
+// value words [2][W], slot table [list] ints, decided bits [list][W] words,
+// partial-sum scratch [list][max(1, N/2)] bytes; W = max(1, N/32).
 __host__ __device__ inline size_t scl_lds_bytes(int log2n, int list) {
     const size_t n = (size_t)1 << log2n;
     const size_t half = n > 1 ? n / 2 : 1;
     const size_t words = n >= 32 ? n / 32 : 1;
-    return (size_t)list * n * 4 + 2 * words * 4 + 4 * (size_t)list + (size_t)list * (n + half);
+    return (size_t)list * n * 4 + 2 * words * 4 + 4 * (size_t)list + (size_t)list * words * 4 + (size_t)list * half;
 }
 
 __global__ __launch_bounds__(64) void k_scl_decode(const FrameDesc* __restrict__ descs, int n_frames, int list,
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(64) void k_scl_decode(const FrameDesc* __restrict__
     uint32_t* mw = reinterpret_cast<uint32_t*>(A + (size_t)list * N);
     uint32_t* vw = mw + W;
     int* phys = reinterpret_cast<int*>(vw + W);
-    uint8_t* U = reinterpret_cast<uint8_t*>(phys + list);
-    uint8_t* Bt = U + (size_t)list * N;
+    uint32_t* U = reinterpret_cast<uint32_t*>(phys + list);  // bit i of word i/32: decision of leaf i
+    uint8_t* Bt = reinterpret_cast<uint8_t*>(U + (size_t)list * W);
     const int lane = (int)threadIdx.x;
 
     for (int w = lane; w < W; w += 64) {
@@ -117,7 +117,8 @@ __global__ __launch_bounds__(64) void k_scl_decode(const FrameDesc* __restrict__
                 const int idx = base + lane;
                 if (idx < total) {
                     const int s = phys[idx >> t], j = idx & (h - 1);
-                    Bt[(size_t)s * NB + j] = U[(size_t)s * N + i - h + j];
+                    const int e = i - h + j;
+                    Bt[(size_t)s * NB + j] = (uint8_t)((U[(size_t)s * W + (e >> 5)] >> (e & 31)) & 1u);
                 }
             }
             for (int q = 1; q < h; q <<= 1)
@@ -142,7 +143,8 @@ __global__ __launch_bounds__(64) void k_scl_decode(const FrameDesc* __restrict__
             const int b = (int)((vw[i >> 5] >> (i & 31)) & 1u);
             if (lane < active) {
                 if ((b != 0) != hard) pm = pm + fabsf(lam);
-                U[(size_t)phys[lane] * N + i] = (uint8_t)b;
+                uint32_t* w = U + (size_t)phys[lane] * W + (i >> 5);
+                *w = (*w & ~(1u << (i & 31))) | ((uint32_t)b << (i & 31));
             }
             continue;
         }
@@ -195,11 +197,16 @@ __global__ __launch_bounds__(64) void k_scl_decode(const FrameDesc* __restrict__
             const int p = __shfl(new_parent, r);
             const int src = phys[p];
             if (lane == r) new_slot = s;
-            // copy the parent's LLRs and decisions 0 .. i-1 into the fresh slot
-            for (int e = lane; e < N; e += 64) {
-                A[(size_t)s * N + e] = A[(size_t)src * N + e];
-                if (e < i) U[(size_t)s * N + e] = U[(size_t)src * N + e];
+            // copy what the new path will read of its parent: the node LLRs at
+            // the depths d whose node holds leaf i in its left half (their
+            // right child's g is still to come; the other depths are
+            // rewritten before they are read), and the decisions 0 .. i-1
+            for (int d = 1; d < n; ++d) {
+                if ((i >> (n - 1 - d)) & 1) continue;
+                const int off = depth_off(N, d), sz = N >> d;
+                for (int e = lane; e < sz; e += 64) A[(size_t)s * N + off + e] = A[(size_t)src * N + off + e];
             }
+            for (int e = lane; e <= (i >> 5); e += 64) U[(size_t)s * W + e] = U[(size_t)src * W + e];
         }
         // new slot table: ranks first, then the free slots
         uint32_t rest = free_slots;
@@ -210,7 +217,10 @@ __global__ __launch_bounds__(64) void k_scl_decode(const FrameDesc* __restrict__
             if (lane == r) slot_here = s;
         }
         if (lane < list) phys[lane] = slot_here;
-        if (lane < keep) U[(size_t)slot_here * N + i] = (uint8_t)new_bit;
+        if (lane < keep) {
+            uint32_t* w = U + (size_t)slot_here * W + (i >> 5);
+            *w = (*w & ~(1u << (i & 31))) | ((uint32_t)new_bit << (i & 31));
+        }
         pm = lane < keep ? new_pm : 0.0f;
         active = keep;
     }
@@ -226,14 +236,8 @@ __global__ __launch_bounds__(64) void k_scl_decode(const FrameDesc* __restrict__
         }
     }
     const int sb = phys[best];
-    for (int base = 0; base < N; base += 64) {
-        const bool bit = base + lane < N && U[(size_t)sb * N + base + lane] != 0;
-        const uint64_t w = __ballot(bit);
-        if (lane == 0) {
-            fd.uhat[base >> 5] = (uint32_t)w;
-            if (base + 32 < N) fd.uhat[(base >> 5) + 1] = (uint32_t)(w >> 32);
-        }
-    }
+    const uint32_t low = N < 32 ? (1u << N) - 1u : 0xffffffffu;
+    for (int e = lane; e < W; e += 64) fd.uhat[e] = U[(size_t)sb * W + e] & low;
     if (pm_out && lane == 0) pm_out[f] = best_pm;
 }
 
