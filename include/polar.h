@@ -234,6 +234,11 @@ typedef struct polar_ctx polar_ctx;
  * Create a decoding context on a device.  The context owns only host-side
  * state (options, a pinned staging buffer for frame descriptors); device
  * scratch is the caller's workspace, attached with polar_ctx_set_workspace.
+ * Every call that runs in that workspace (polar_sc_decode_batch, _plain,
+ * polar_scl_decode_batch, polar_autotune) reuses it from its start: the
+ * caller orders such calls on the device (one stream, or events).  Calls
+ * given their own workspace (polar_fer_bsc, polar_construct_degrade) or
+ * arena (serving) are independent of it.
  *   device     HIP device ordinal
  *   workspace  device pointer or NULL (attach later)
  *   ws_bytes   size of workspace in bytes
