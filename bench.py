@@ -344,6 +344,7 @@ def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, loads=SERVE_LOAD
         done = 0
         nxt = 0
         max_batches = 0
+        max_arena = 0
         t0 = time.perf_counter()
         while done < len(reqs):
             now = time.perf_counter() - t0
@@ -355,25 +356,28 @@ def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, loads=SERVE_LOAD
                     raise RuntimeError(f"request {rid} failed with {st}")
                 lat[rid] = l
                 done += 1
-            max_batches = max(max_batches, srv.stats()[0])
+            st = srv.stats()
+            max_batches = max(max_batches, st[0])
+            max_arena = max(max_arena, st[1])
         wall = time.perf_counter() - t0
         srv.close()
-        return wall, lat, max_batches
+        return wall, lat, max_batches, max_arena
 
     def pct(x, q):
         return round(float(np.percentile(x, q)) * 1e3, 3)
 
     # saturation: everything queued at t = 0
     run(np.zeros(len(reqs)))  # warm-up
-    wall_sat, lat_sat, mb_sat = run(np.zeros(len(reqs)))
+    wall_sat, lat_sat, mb_sat, arena_sat = run(np.zeros(len(reqs)))
     sat_mbit = bits.sum() / wall_sat / 1e6
     sweep = []
     for load in loads:
         rate = load * sat_mbit * 1e6 / bits.mean()  # requests per second
         arrivals = np.cumsum(g.exponential(1.0 / rate, len(reqs)))
-        wall, lat, mb = run(arrivals)
+        wall, lat, mb, arena_max = run(arrivals)
         row = dict(load=load, arrival_rate_req_s=round(rate, 1), Mbit_s=round(bits.sum() / wall / 1e6, 1),
-                   p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), max_batches_resident=mb)
+                   p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), p999_ms=pct(lat, 99.9), max_batches_resident=mb,
+                   max_arena_bytes_in_use=int(arena_max))
         row["by_log2n"] = {str(l): dict(p50_ms=pct(lat[logs == l], 50), p99_ms=pct(lat[logs == l], 99))
                            for l in sizes if (logs == l).any()}
         sweep.append(row)
@@ -381,7 +385,8 @@ def serve_leg(lp, torch, dev, n_requests=2000, pool_per_size=8, loads=SERVE_LOAD
     return dict(requests=len(reqs), mix="N=2^16/2^20/2^22 at 0.5/0.35/0.15; BSC p=0.03 R=0.75 and BIAWGN "
                 "sigma=0.97 R=0.45 (min-sum), Poisson arrivals",
                 saturation_Mbit_s=round(sat_mbit, 1), saturation_p50_ms=pct(lat_sat, 50),
-                saturation_p99_ms=pct(lat_sat, 99), load=0.8, Mbit_s=head["Mbit_s"], p50_ms=head["p50_ms"],
+                saturation_p99_ms=pct(lat_sat, 99), saturation_max_arena_bytes_in_use=int(arena_sat),
+                load=0.8, Mbit_s=head["Mbit_s"], p50_ms=head["p50_ms"],
                 p99_ms=head["p99_ms"], sweep=sweep, arena_bytes=arena_bytes,
                 note="latency = host time from submit to the poll that sees the request's own frame done; "
                      "each request is charged its own footprint in the arena")

@@ -20,6 +20,18 @@ int fail(int code, const char* fmt, ...);
 int ok();
 int hip_fail(hipError_t e, const char* what);
 
+// A roctx range for the lifetime of the object (shown by rocprofv3
+// --marker-trace around each library call's host work and launches).
+struct TraceRange {
+    explicit TraceRange(const char* name);
+    ~TraceRange();
+};
+
+// Diagnostic log to stderr, on when the environment variable POLAR_LOG is
+// set to a non-empty value other than 0 (read once).
+bool log_on();
+void log_line(const char* fmt, ...);
+
 // Keeps the caller's current device unchanged across a call.
 struct DeviceGuard {
     int prev = -1;

@@ -216,6 +216,7 @@ extern "C" size_t polar_construct_workspace_bytes(int log2n, int mu, int m0) {
 
 extern "C" int polar_construct_degrade(int log2n, const double* w0, int m0, int mu, void* workspace,
                                        size_t ws_bytes, double* pe, void* stream) {
+    TraceRange tr("polar_construct_degrade");
     if (log2n < 0 || log2n > POLAR_MAX_LOG2N) return fail(POLAR_E_INVAL, "log2n %d outside 0..%d", log2n, POLAR_MAX_LOG2N);
     if (mu < 2 || mu > POLAR_CONSTRUCT_MAX_MU) return fail(POLAR_E_INVAL, "mu %d outside 2..%d", mu, POLAR_CONSTRUCT_MAX_MU);
     if (m0 < 1 || m0 > POLAR_CONSTRUCT_MAX_OUTPUTS)

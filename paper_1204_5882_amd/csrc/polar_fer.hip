@@ -252,6 +252,7 @@ extern "C" size_t polar_fer_workspace_bytes(const polar_ctx* c, const polar_fer_
 
 extern "C" int polar_fer_bsc(polar_ctx* c, const polar_fer_cfg* cfg, void* workspace, size_t ws_bytes,
                              uint32_t* bit_errors, polar_fer_result* out, void* stream) {
+    TraceRange tr("polar_fer_bsc");
     if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
     int rc = check_cfg(cfg);
     if (rc) return rc;

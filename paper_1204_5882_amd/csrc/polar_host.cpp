@@ -9,10 +9,13 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "host_internal.h"
 #include "sc_device.h"
@@ -34,6 +37,27 @@ int fail(int code, const char* fmt, ...) {
 }
 
 int ok() { return POLAR_OK; }
+
+TraceRange::TraceRange(const char* name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
+
+bool log_on() {
+    static const bool on = [] {
+        const char* v = std::getenv("POLAR_LOG");
+        return v != nullptr && v[0] != 0 && !(v[0] == '0' && v[1] == 0);
+    }();
+    return on;
+}
+
+void log_line(const char* fmt, ...) {
+    if (!log_on()) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[libpolar] %s\n", buf);
+}
 
 int hip_fail(hipError_t e, const char* what) {
     return fail(POLAR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -590,12 +614,19 @@ int run_plan(polar_ctx* c, const Plan& p, void* ws, size_t ws_bytes, hipStream_t
 }
 
 int decode_impl(polar_ctx* c, const polar_frame* frames, int n_frames, void* stream, bool plain) {
+    TraceRange tr(plain ? "polar_sc_decode_plain" : "polar_sc_decode_batch");
     if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
     int rc = validate_frames(frames, n_frames);
     if (rc) return rc;
     if (n_frames == 0) return ok();
     Plan p;
     make_plan(c, frames, n_frames, plain, p);
+    if (log_on())
+        for (const auto& g : p.groups)
+            log_line("decode: f_kind %d dump %d, %d frames (largest 2^%d): cutover %d, %d waves, %d slots + %d "
+                     "helpers, %d frames per small workgroup, prune %d; workspace %zu bytes",
+                     g.fk, g.dump, g.count, g.hist.maxlog, g.cfg.cutover, g.cfg.waves, g.cfg.slots, g.cfg.helpers,
+                     g.cfg.fwg, g.cfg.prune, p.total);
     if (!c->ws || c->ws_bytes < p.total)
         return fail(POLAR_E_NOMEM, "workspace of %zu bytes < %zu required", c->ws_bytes, p.total);
     DeviceGuard g(c->device);

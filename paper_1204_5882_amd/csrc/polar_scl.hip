@@ -250,6 +250,7 @@ extern "C" size_t polar_scl_workspace_bytes(int n_frames) {
 
 extern "C" int polar_scl_decode_batch(polar_ctx* c, const polar_frame* frames, int n_frames, int list_size,
                                       float* path_metric, void* stream) {
+    TraceRange tr("polar_scl_decode_batch");
     if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
     if (list_size < 1 || list_size > POLAR_SCL_MAX_LIST)
         return fail(POLAR_E_INVAL, "list size %d outside 1..%d", list_size, POLAR_SCL_MAX_LIST);

@@ -221,6 +221,8 @@ int launch(polar_server* s) {
             p.descs[k].done_val = r.ticket;
         }
         // the batch starts after the work already enqueued on the input stream
+        TraceRange tr("polar_serve batch");
+        log_line("serve: batch of %zu requests, %zu workspace bytes", p.descs.size(), need);
         hipError_t e = hipEventRecord(b.inputs, s->input_stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.inputs, 0);
         int rc = e == hipSuccess ? run_plan(c, p, s->arena + off, need, b.stream, b.stager, false, s->flags)

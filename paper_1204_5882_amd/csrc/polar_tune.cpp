@@ -65,6 +65,7 @@ int time_candidate(polar_ctx* c, const polar_frame* frames, int n_frames, const 
 extern "C" int polar_autotune(polar_ctx* c, const polar_frame* frames, int n_frames, int reps, void* stream,
                               int* best_cutover, int* best_waves, int* best_slots, int* best_fwg, int* best_prune,
                               double* best_ms, int* n_candidates) {
+    TraceRange tr("polar_autotune");
     if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
     int rc = validate_frames(frames, n_frames);
     if (rc) return rc;
