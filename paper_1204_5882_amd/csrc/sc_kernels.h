@@ -315,13 +315,18 @@ __device__ __forceinline__ float gupd(float a, float b, uint32_t sgn) {
 // is SC by construction; its children are checked again.
 //   saturating min-sum (FK = 2): as min-sum (a saturated sum of two terms of
 //            the sign of b keeps that sign and is nonzero);
-//   phi table (FK = 3): the table update can round a nonzero result to 0
-//            anywhere, so no floor holds: rate-1 nodes are always descended.
+//   phi table (FK = 3): the update can round a nonzero result to 0 (f of
+//            1 and -1 is -0), but T[i] = 0 for every i >= 67 (phi(67/16) 16
+//            = 0.486 rounds to 0), so for |a|, |b| >= 67 the sum of lookups
+//            is 0 and the update is min(T[0], |a|, |b|) = min(|a|, |b|): f is
+//            min-sum there and keeps the bound, as g does, so inputs of 67
+//            and above (floor 66, any L) make the hard decisions SC.  67 is
+//            the least bound closed under f: T[T[66] + T[66]] = T[2] = 44.
 template <int FK>
 __host__ __device__ constexpr float rate1_floor(int L) {
     return (FK == 0 || FK == 2) ? 0.0f
            : FK == 1            ? 1.0f + 0.69314718f * (float)L + 0.01f
-                                : __builtin_inff();
+                                : 66.0f;
 }
 
 // |x| <= floor, evaluated on the magnitude bits (non-negative floats order
@@ -483,6 +488,22 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
         const uint32_t Z = (uint32_t)((ballot(a == 0.0f) >> O) & ALL);
         const uint64_t bits = (uint64_t)r1_bits<M>(S, Z) << O;
         return lane_bit(bits) ? SIGN : 0u;
+    } else if constexpr (P == 0 && (FK == 1 || FK == 3) && M >= 2) {
+        // the exact updates have no three-state rule: hard decisions when no
+        // input is at or under the floor, else the node's plain recursion
+        constexpr int H = M / 2;
+        const uint64_t low = ballot(below_rate1_floor<FK, LG>(a));
+        uint32_t bn;
+        if (((low >> O) & ALL) == 0) {
+            bn = dec_sign(a);
+        } else {
+            const float c = fupd<FK>(a, lane_downf<H>(a));
+            const uint32_t bl = sl_node<H, 0, FK, DUMP>(c, O, B);
+            const float d = gsat<FK>(a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bl)));
+            const uint32_t br = sl_node<H, 0, FK, DUMP>(d, O + H, B);
+            bn = sel_lanes(left_lanes<H>(), bl ^ lane_down<H>(br), br);
+        }
+        return bn;
     } else if constexpr (P == (ALL >> 1)) {
         const float last = rep_chain<M / 2, M, FK>(a, B);  // repetition
         const int il = O + M - 1;

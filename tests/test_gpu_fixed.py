@@ -152,3 +152,34 @@ def test_fixed_point_mixed_with_float_kinds_in_one_batch():
         elif fk == 0:
             assert np.array_equal(u, oracle.sc_decode(*fr)[0])
     ctx.close()
+
+
+@pytest.mark.parametrize("log2n", [1, 2, 5, 6, 7, 10, 12, 14])
+def test_phi_rate1_floor_boundary(log2n):
+    """Rate-1 nodes whose input magnitudes sit on both sides of the phi
+    update's rate-1 floor (67 in units of 2^-4), so that the kernel's floor
+    tests go both ways at every node size, pruned and unpruned."""
+    g = np.random.default_rng(3700 + log2n)
+    n = 1 << log2n
+    mags = np.array([1, 2, 44, 55, 56, 65, 66, 67, 68, 69, 134, 1000])
+    frames = []
+    for k in range(8):
+        if k % 4 == 0:
+            mag = g.choice(mags, n)
+        elif k % 4 == 1:
+            mag = g.choice([66, 67], n)
+        elif k % 4 == 2:
+            mag = np.where(g.random(n) < 0.02, g.choice([1, 66], n), g.integers(67, 200, n))
+        else:
+            mag = g.choice([56, 67, 68], n)
+        llr = (mag * (1 - 2 * g.integers(0, 2, n))).astype(np.float32)
+        mask = np.zeros(n, np.uint8) if k < 4 else (g.random(n) < [0.1, 0.3, 0.5, 0.05][k - 4]).astype(np.uint8)
+        fval = (g.integers(0, 2, n) & mask).astype(np.uint8)
+        frames.append((llr, mask, fval))
+    for prune in (True, False):
+        _say(f"case: phi floor log2n={log2n} prune={prune}")
+        us, _ = decode(frames, f_kind=3, prune=prune)
+        _check(frames, 3, us, what=f"prune={prune}")
+    _say(f"case: phi floor log2n={log2n} pruned leaf dump")
+    us, leaves = decode(frames, f_kind=3, prune=True, dump=True)
+    _check(frames, 3, us, leaves, computed_only=True, what="pruned dump")

@@ -272,3 +272,63 @@ def test_hot_patterns_cover_most_mixed_blocks():
     full = np.uint64(0xFFFFFFFFFFFFFFFF)
     mixed = [int(p) for p in pats if p not in (0, full, full >> np.uint64(1))]
     assert sum(p in p64 for p in mixed) / len(mixed) > 0.5
+
+
+# ---------------------------------------------------------------------------
+# Rate-1 floor of the phi-table update (fixed point, units of 2^-4): with
+# every input magnitude at or above 67 the table update is min(|a|, |b|)
+# (T[i] = 0 for i >= 67, so the sum of lookups is 0 and T[0] caps nothing),
+# which keeps the bound, and g in a rate-1 node adds two terms of one sign:
+# the partial sums are the hard decisions.  Below it they need not be.
+# ---------------------------------------------------------------------------
+PHI_FLOOR = 67
+
+
+def _kernel_phi_floor():
+    src = open(SRC).read()
+    body = src[src.index("constexpr float rate1_floor(int L)"):]
+    body = body[: body.index("\n}\n")]
+    return float(re.search(r":\s*([0-9.]+)f;", body).group(1))
+
+
+def test_phi_floor_from_the_table():
+    t = oracle.phi_table()
+    assert t[PHI_FLOOR - 1] > 0 and np.all(t[PHI_FLOOR:] == 0)
+    # the least bound B with f(a, b) >= B whenever |a|, |b| >= B
+    closed = [b for b in range(1, t.size) if oracle.f_fixed(oracle.FIXED_PHI, b, b) >= b]
+    assert closed[0] == PHI_FLOOR
+    assert oracle.f_fixed(oracle.FIXED_PHI, PHI_FLOOR - 1, PHI_FLOOR - 1) == 44
+    g = np.random.default_rng(11)
+    for a, b in itertools.chain(itertools.product(range(PHI_FLOOR, PHI_FLOOR + 200), (PHI_FLOOR, 300)),
+                                g.integers(PHI_FLOOR, oracle.FIXED_MAX + 1, (2000, 2))):
+        for sa, sb in ((1, 1), (1, -1), (-1, 1), (-1, -1)):
+            assert oracle.f_fixed(oracle.FIXED_PHI, sa * int(a), sb * int(b)) == sa * sb * min(int(a), int(b))
+    # the kernel descends every rate-1 node with an input magnitude <= its floor
+    assert _kernel_phi_floor() == PHI_FLOOR - 1
+
+
+@pytest.mark.parametrize("m", [2, 8, 64, 1024])
+def test_phi_rate1_above_floor_is_hard_decision(m):
+    g = np.random.default_rng(300 + m)
+    zero = np.zeros(m, np.uint8)
+    for trial in range(60):
+        mag = g.choice([PHI_FLOOR, PHI_FLOOR + 1, 100, 1000, oracle.FIXED_MAX], m) if trial % 2 else \
+            g.integers(PHI_FLOOR, oracle.FIXED_MAX + 1, m)
+        llr = (mag * (1 - 2 * g.integers(0, 2, m))).astype(np.int32)
+        u, _ = oracle.sc_decode_fixed(llr, zero, zero, oracle.FIXED_PHI)
+        x = oracle.encode(m.bit_length() - 1, u)
+        assert np.array_equal(x, (llr < 0).astype(np.uint8))
+
+
+def test_phi_rate1_below_floor_is_not_hard_decision():
+    # f(1, -1) = -0 decides 0, then g = -1 + 1 = 0 decides 0: x-hat = (0, 0), hard (0, 1)
+    u, _ = oracle.sc_decode_fixed(np.array([1, -1], np.int32), np.zeros(2, np.uint8), np.zeros(2, np.uint8),
+                                  oracle.FIXED_PHI)
+    assert oracle.encode(1, u).tolist() == [0, 0]
+    g = np.random.default_rng(12)
+    differs = 0
+    for _ in range(200):
+        llr = (g.integers(1, PHI_FLOOR, 64) * (1 - 2 * g.integers(0, 2, 64))).astype(np.int32)
+        u, _ = oracle.sc_decode_fixed(llr, np.zeros(64, np.uint8), np.zeros(64, np.uint8), oracle.FIXED_PHI)
+        differs += not np.array_equal(oracle.encode(6, u), (llr < 0).astype(np.uint8))
+    assert differs > 0
