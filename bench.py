@@ -90,15 +90,16 @@ HBM_PEAK_GBS = 8000.0
 CUTOVER_FOR_MODEL = 12
 
 
-def bytes_per_bit(log2n: int) -> float:
+def bytes_per_bit(log2n: int, level_bytes: int = 4) -> float:
     """Algorithmic HBM bytes per decoded bit when only 2^12 leaves fit on chip:
-    8 B/bit per HBM-resident depth (each level written once and read once, the
-    root read twice, f chains fused), 0.25 B/bit per depth of partial sums and
-    0.375 B/bit of frozen mask, frozen values and u-hat."""
+    the FP32 root read twice (8 B/bit), every other HBM-resident depth written
+    once and read once (2 x level_bytes per bit: 4-byte floats, or the
+    fixed-point kinds' 2-byte integers; f chains fused), 0.25 B/bit per depth
+    of partial sums and 0.375 B/bit of frozen mask, frozen values and u-hat."""
     d = max(0, log2n - CUTOVER_FOR_MODEL)
     if d == 0:
         return 4.0 + 0.375
-    return 8.0 * d + 0.25 * d + 0.375
+    return 8.0 + 2.0 * level_bytes * (d - 1) + 0.25 * d + 0.375
 
 
 CONFIGS = {
@@ -621,7 +622,8 @@ def main(argv=None):
     value = total_bits / (ms_step / 1e3) / 1e6
 
     # roofline of the decode kernel: algorithmic bytes / measured launch time
-    alg_bytes = sum((1 << it["log2n"]) * bytes_per_bit(it["log2n"]) for it in items)
+    level_bytes = 2 if cfg["fkind"] >= 2 else 4  # the fixed-point kinds keep HBM levels as int16
+    alg_bytes = sum((1 << it["log2n"]) * bytes_per_bit(it["log2n"], level_bytes) for it in items)
     achieved = alg_bytes / (ev_ms / 1e3) / 1e9
     source = decoder_source_hash()
     tr = measured_traffic(args.config, source) if (cfg["fkind"] == 0 and args.prune and not args.cutover) else None

@@ -52,7 +52,9 @@ extern "C" {
    The frame's llr array holds integers in units of 2^-POLAR_FIXED_FRAC with
    |L| <= POLAR_FIXED_MAX, stored as float (exact); every variable update
    g = b +- a saturates to +-POLAR_FIXED_MAX; leaf LLRs come out in the same
-   units.  Results are bit-exact against integer arithmetic. */
+   units.  Results are bit-exact against integer arithmetic.  Other llr values
+   give undefined results (the decoder keeps its large LLR levels in the
+   workspace as 16-bit integers). */
 #define POLAR_F_MINSUM_Q16 2 /* saturating min-sum                               */
 #define POLAR_F_PHI_Q16 3    /* sign(a) sign(b) min(T[min(T[|a|] + T[|b|], 255)], |a|, |b|),
                                 T[i] = round(phi(i 2^-4) 2^4), phi(x) = -ln tanh(x/2),

@@ -992,6 +992,35 @@ __device__ __forceinline__ int64_t row_here(int wave) {
 }
 __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
 
+// Level storage.  The FP32 kinds keep every level as float.  The fixed-point
+// kinds keep the levels that live in HBM as int16, which is exact (every
+// value is an integer within +-32767) and halves the bytes of the sweeps that
+// HBM bounds; the channel input and the LDS levels stay float.  (A zero loses
+// its sign in int16, which no decision or later update depends on: decisions
+// test L < 0, f and g give zeros of equal magnitude either way.)
+// Raw loads (4 elements: a float4, or 4 int16 in an int2) and their
+// conversion to float, kept apart so that a sweep converts only where it uses
+// the values and holds the narrow form while its loads are in flight.
+__device__ __forceinline__ float4 ldraw(const float* p) { return ld4(p); }
+__device__ __forceinline__ int2 ldraw(const int16_t* p) { return *reinterpret_cast<const int2*>(p); }
+__device__ __forceinline__ float4 cvt4(float4 v) { return v; }
+__device__ __forceinline__ float4 cvt4(int2 w) {
+    return make_float4((float)(((int32_t)((uint32_t)w.x << 16)) >> 16), (float)(w.x >> 16),
+                       (float)(((int32_t)((uint32_t)w.y << 16)) >> 16), (float)(w.y >> 16));
+}
+template <typename T>
+__device__ __forceinline__ float4 ldv(const T* p) { return cvt4(ldraw(p)); }
+__device__ __forceinline__ void stv(float* p, float4 v) { st4(p, v); }
+__device__ __forceinline__ void stv(int16_t* p, float4 v) {
+    const uint32_t a = (uint32_t)(int32_t)v.x & 0xffffu, b = (uint32_t)(int32_t)v.y;
+    const uint32_t c = (uint32_t)(int32_t)v.z & 0xffffu, d = (uint32_t)(int32_t)v.w;
+    *reinterpret_cast<int2*>(p) = make_int2((int32_t)(a | (b << 16)), (int32_t)(c | (d << 16)));
+}
+
+// Element types of a two-level sweep's input, middle and output levels, one
+// bit each (set: int16): LV_IN, LV_MID, LV_OUT.
+enum : uint32_t { LV_IN = 1u, LV_MID = 2u, LV_OUT = 4u };
+
 template <int FK>
 __device__ __forceinline__ float4 f4(float4 a, float4 b) {
     return make_float4(fupd<FK>(a.x, b.x), fupd<FK>(a.y, b.y), fupd<FK>(a.z, b.z), fupd<FK>(a.w, b.w));
@@ -1068,10 +1097,12 @@ __device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t ha
 // Each lane takes elements j .. j+3 of out and produces mid[j], mid[j + h/2]
 // (and their 4-wide neighbours) from in[j], in[j + h], in[j + h/2],
 // in[j + h/2 + h]: mid is written for its later g but not read back.
-template <int C, int FK, bool G>
-__device__ __forceinline__ void sweep2(const float* __restrict__ in, int64_t h, const uint64_t* __restrict__ beta,
-                                       float* __restrict__ mid, float* __restrict__ out, int wave, int nw) {
-    constexpr int U = SWEEP_UNROLL / 4;
+template <int C, int FK, bool G, typename TI = float, typename TM = float, typename TO = float>
+__device__ __forceinline__ void sweep2(const TI* __restrict__ in, int64_t h, const uint64_t* __restrict__ beta,
+                                       TM* __restrict__ mid, TO* __restrict__ out, int wave, int nw) {
+    // rows in flight: int16 input moves half the bytes per row, so twice the
+    // rows keep the same bytes (and registers) in flight
+    constexpr int U = SWEEP_UNROLL / 4 * (sizeof(TI) == 2 ? 2 : 1);
     const int l4 = lane_id_here() * 4;
     const int64_t q = h >> 1;
     const int64_t rows = q >> 8;
@@ -1080,34 +1111,66 @@ __device__ __forceinline__ void sweep2(const float* __restrict__ in, int64_t h, 
         else return f4<FK>(a, b);
     };
     int64_t r = row_here(wave);
+    using Raw = decltype(ldraw(in));
     for (; r + (U - 1) * nw < rows; r += U * nw) {
-        float4 a0[U], b0[U], a1[U], b1[U];
+        Raw a0[U], b0[U], a1[U], b1[U];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const int64_t j = (r + i * nw) * 256 + l4;
-            a0[i] = ld4(in + j);
-            b0[i] = ld4(in + j + h);
-            a1[i] = ld4(in + j + q);
-            b1[i] = ld4(in + j + q + h);
+            a0[i] = ldraw(in + j);
+            b0[i] = ldraw(in + j + h);
+            a1[i] = ldraw(in + j + q);
+            b1[i] = ldraw(in + j + q + h);
         }
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const int64_t j = (r + i * nw) * 256 + l4;
-            const float4 m0 = first(a0[i], b0[i], j);
-            const float4 m1 = first(a1[i], b1[i], j + q);
-            st4(mid + j, m0);
-            st4(mid + j + q, m1);
-            st4(out + j, f4<FK>(m0, m1));
+            const float4 m0 = first(cvt4(a0[i]), cvt4(b0[i]), j);
+            const float4 m1 = first(cvt4(a1[i]), cvt4(b1[i]), j + q);
+            stv(mid + j, m0);
+            stv(mid + j + q, m1);
+            stv(out + j, f4<FK>(m0, m1));
         }
     }
     for (; r < rows; r += nw) {
         const int64_t j = r * 256 + l4;
-        const float4 m0 = first(ld4(in + j), ld4(in + j + h), j);
-        const float4 m1 = first(ld4(in + j + q), ld4(in + j + q + h), j + q);
-        st4(mid + j, m0);
-        st4(mid + j + q, m1);
-        st4(out + j, f4<FK>(m0, m1));
+        const float4 m0 = first(ldv(in + j), ldv(in + j + h), j);
+        const float4 m1 = first(ldv(in + j + q), ldv(in + j + q + h), j + q);
+        stv(mid + j, m0);
+        stv(mid + j + q, m1);
+        stv(out + j, f4<FK>(m0, m1));
     }
+}
+
+// sweep2 on levels of the element types given by the LV_ bits (only the
+// fixed-point kinds have int16 levels; the combinations are those of three
+// consecutive depths: input or int16, then int16 or float).
+template <int C, int FK, bool G>
+__device__ __forceinline__ void sweep2_lv(uint32_t types, const float* in, int64_t h, const uint64_t* beta, float* mid,
+                                          float* out, int wave, int nw) {
+    if constexpr (FK >= 2) {
+        using I = int16_t;
+        switch (types) {
+            case LV_IN | LV_MID | LV_OUT:
+                sweep2<C, FK, G, I, I, I>((const I*)in, h, beta, (I*)mid, (I*)out, wave, nw);
+                return;
+            case LV_IN | LV_MID:
+                sweep2<C, FK, G, I, I, float>((const I*)in, h, beta, (I*)mid, out, wave, nw);
+                return;
+            case LV_IN:
+                sweep2<C, FK, G, I, float, float>((const I*)in, h, beta, mid, out, wave, nw);
+                return;
+            case LV_MID | LV_OUT:
+                sweep2<C, FK, G, float, I, I>(in, h, beta, (I*)mid, (I*)out, wave, nw);
+                return;
+            case LV_MID:
+                sweep2<C, FK, G, float, I, float>(in, h, beta, (I*)mid, out, wave, nw);
+                return;
+            default:
+                break;
+        }
+    }
+    sweep2<C, FK, G>(in, h, beta, mid, out, wave, nw);
 }
 
 // beta[0 .. words) ^= beta[words .. 2 words)
@@ -1162,11 +1225,13 @@ __device__ __forceinline__ int claim_part(SweepBox* b, uint32_t seq, int* parts_
     }
 }
 
+// op: bit 0 set for a g first, bits 1..3 the levels' LV_ bits.
 template <int C, int FK>
 __device__ __forceinline__ void run_part(int op, const float* in, int64_t h, const uint64_t* beta, float* mid,
                                          float* out, int part, int parts, int wave, int W) {
-    if (op) sweep2<C, FK, true>(in, h, beta, mid, out, part * W + wave, parts * W);
-    else sweep2<C, FK, false>(in, h, nullptr, mid, out, part * W + wave, parts * W);
+    const uint32_t types = (uint32_t)op >> 1;
+    if (op & 1) sweep2_lv<C, FK, true>(types, in, h, beta, mid, out, part * W + wave, parts * W);
+    else sweep2_lv<C, FK, false>(types, in, h, nullptr, mid, out, part * W + wave, parts * W);
 }
 
 // Per-workgroup state of the cooperative sweeps, kept in LDS and read
@@ -1193,12 +1258,12 @@ constexpr bool coop_variant() {
 // the workgroup has a mailbox.  Ends with the workgroup synchronised and the
 // outputs visible to it.
 template <int C, int FK, bool G, bool COOP>
-__device__ __forceinline__ void coop_sweep2(bool shareable, CoopState* cs, const float* in, int64_t h,
+__device__ __forceinline__ void coop_sweep2(bool shareable, CoopState* cs, uint32_t types, const float* in, int64_t h,
                                             const uint64_t* beta, float* mid, float* out, int wave, int W) {
     const int64_t rows = (h >> 1) >> 8;
     SweepBox* box = COOP && shareable ? *(SweepBox* volatile*)&cs->box : nullptr;
     if (!COOP || box == nullptr || rows < COOP_MIN_ROWS) {
-        sweep2<C, FK, G>(in, h, beta, mid, out, wave, W);
+        sweep2_lv<C, FK, G>(types, in, h, beta, mid, out, wave, W);
         __syncthreads();
         return;
     }
@@ -1212,7 +1277,7 @@ __device__ __forceinline__ void coop_sweep2(bool shareable, CoopState* cs, const
     __syncthreads();  // every thread has read seq before thread 0 advances it
     if (threadIdx.x == 0) {
         cs->seq = seq;
-        box->op = G ? 1 : 0;
+        box->op = (int32_t)((G ? 1u : 0u) | (types << 1));
         box->in = in;
         box->beta = beta;
         box->mid = mid;
@@ -1233,7 +1298,7 @@ __device__ __forceinline__ void coop_sweep2(bool shareable, CoopState* cs, const
         __syncthreads();
         if (p < 0) break;
         ++own;
-        run_part<C, FK>(G ? 1 : 0, in, h, beta, mid, out, p, parts, wave, W);
+        run_part<C, FK>((int)((G ? 1u : 0u) | (types << 1)), in, h, beta, mid, out, p, parts, wave, W);
     }
     if (threadIdx.x == 0) {
         // partitions claimed by other workgroups are running and end on their
@@ -1347,6 +1412,17 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
         if (d == D - 2) return tier + (2 << C);
         return reinterpret_cast<float*>(slot + slot_level_offset(n, d));
     };
+    // LV_ bits of a sweep whose input, middle and output levels are at depths
+    // d, d + 1, d + 2 (the last in LDS when it is the cutover depth): the
+    // fixed-point kinds' HBM levels, depths 1 .. D - 3, are int16
+    const auto lv_types = [&](int d) -> uint32_t {
+        if constexpr (FK >= 2) {
+            const auto hbm = [&](int e) { return e >= 1 && e <= D - 3; };
+            return (hbm(d) ? LV_IN : 0u) | (hbm(d + 1) ? LV_MID : 0u) | (hbm(d + 2) ? LV_OUT : 0u);
+        } else {
+            return 0u;
+        }
+    };
     const int64_t nsub = (int64_t)1 << D;
     // mask and value words of subtree s: LDS buffer s & 1, filled by wave 1
     // while wave 0 decodes the subtree before it
@@ -1383,8 +1459,8 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
                 __syncthreads();
             } else {
                 // both outputs in HBM (t >= 4) can be shared with helpers
-                coop_sweep2<C, FK, true, coop_variant<C, FK, PRUNE, DUMP>()>(t >= 4, cs, level(dp), half, bl,
-                                                                             level(D - t), level(D - t + 1), wave, W);
+                coop_sweep2<C, FK, true, coop_variant<C, FK, PRUNE, DUMP>()>(
+                    t >= 4, cs, lv_types(dp), level(dp), half, bl, level(D - t), level(D - t + 1), wave, W);
             }
         }
         // rest of the f chain down to the cutover depth (the cutover node goes
@@ -1392,9 +1468,9 @@ __device__ __forceinline__ void decode_frame(const FrameDesc& fd, uint8_t* slot,
         int d = (s == 0) ? 1 : D - t + 2;
         for (; d + 1 <= D; d += 2) {
             // outputs at depths d, d + 1 <= D - 3 are in HBM: shareable
-            coop_sweep2<C, FK, false, coop_variant<C, FK, PRUNE, DUMP>()>(d + 1 <= D - 3, cs, level(d - 1), N >> d,
-                                                                          nullptr, level(d),
-                                                                          d + 1 == D ? lds : level(d + 1), wave, W);
+            coop_sweep2<C, FK, false, coop_variant<C, FK, PRUNE, DUMP>()>(
+                d + 1 <= D - 3, cs, lv_types(d - 1), level(d - 1), N >> d, nullptr, level(d),
+                d + 1 == D ? lds : level(d + 1), wave, W);
         }
         if (d == D) {
             sweep_f<FK>(level(d - 1), N >> d, lds, wave, W);
@@ -1493,10 +1569,13 @@ __global__ __launch_bounds__(MAXW * 64) void k_sc_decode(const FrameDesc* __rest
     // workgroups 0 .. n_main-1 decode frames (then help); the rest only help.
     // The cooperative state goes to LDS at once, so that none of it holds
     // registers across the frame loop.
-    const bool main_wg = (int)blockIdx.x < n_main;
-    uint8_t* wg_slot = slots + (int64_t)blockIdx.x * slot_bytes;
+    // (the fixed-point kinds take the workgroup index as a scalar, which keeps
+    // their slot address out of vector registers: their int16 sweeps need those)
+    const unsigned wg = FK >= 2 ? (unsigned)__builtin_amdgcn_readfirstlane((int)blockIdx.x) : blockIdx.x;
+    const bool main_wg = (int)wg < n_main;
+    uint8_t* wg_slot = slots + (int64_t)wg * slot_bytes;
     if (threadIdx.x == 0) {
-        s_coop.box = boxes != nullptr && main_wg ? boxes + blockIdx.x : nullptr;
+        s_coop.box = boxes != nullptr && main_wg ? boxes + wg : nullptr;
         s_coop.boxes = boxes;
         s_coop.n_main = n_main;
         s_coop.seq = 0;
