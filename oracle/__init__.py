@@ -187,6 +187,9 @@ FIXED_FRAC = 4
 FIXED_MAX = 32767
 FIXED_TABLE_LEN = 256
 FIXED_MINSUM, FIXED_PHI = 0, 1
+# Saturating min-sum on 8-bit integers: |L| <= FIXED8_MAX in any units.
+FIXED_MINSUM8 = 2
+FIXED8_MAX = 127
 
 
 def phi_table(frac: int = FIXED_FRAC, length: int = FIXED_TABLE_LEN) -> np.ndarray:

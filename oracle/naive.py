@@ -124,13 +124,15 @@ def brute_sc(llr, frozen, fval, teacher=None):
 
 # ---------------------------------------------------------------------------
 # Fixed point (Section 4: fixed-point LLRs, phi-table check update), per bit.
-# Integers in units of 2^-frac, saturated to +-32767.
+# Integers in units of 2^-frac, saturated to +-32767 (kinds 0 and 1) or to
+# +-127 (kind 2, min-sum on 8-bit integers).
 # ---------------------------------------------------------------------------
 FIXED_MAX = 32767
+FIXED8_MAX = 127
 
 
-def _sat(x: int) -> int:
-    return max(-FIXED_MAX, min(FIXED_MAX, x))
+def _sat(x: int, lim: int) -> int:
+    return max(-lim, min(lim, x))
 
 
 def f_fixed(a: int, b: int, kind: int, table) -> int:
@@ -143,6 +145,7 @@ def f_fixed(a: int, b: int, kind: int, table) -> int:
 
 
 def _leaf_fixed(alpha, i, decided, kind, table):
+    lim = FIXED8_MAX if kind == 2 else FIXED_MAX
     m = len(alpha)
     if m == 1:
         return alpha[0]
@@ -150,7 +153,7 @@ def _leaf_fixed(alpha, i, decided, kind, table):
     if i < h:
         return _leaf_fixed([f_fixed(alpha[j], alpha[j + h], kind, table) for j in range(h)], i, decided, kind, table)
     beta = encode_matrix(decided[:h])
-    return _leaf_fixed([_sat(alpha[j + h] - alpha[j] if beta[j] else alpha[j + h] + alpha[j]) for j in range(h)],
+    return _leaf_fixed([_sat(alpha[j + h] - alpha[j] if beta[j] else alpha[j + h] + alpha[j], lim) for j in range(h)],
                        i - h, decided[h:], kind, table)
 
 

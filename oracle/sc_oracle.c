@@ -319,18 +319,22 @@ int oracle_sc_decode(int log2n, int boxplus, const float* llr, const uint8_t* fr
 /* f = sign(a) sign(b) phi(phi(|a|) + phi(|b|))).                           */
 /*                                                                          */
 /* LLRs are integers in units of 2^-FRAC (FRAC = 4 here), saturated to      */
-/* +-32767 (int16 range).  Two check updates:                               */
+/* +-32767 (int16 range), or for kind 2 to +-127 (int8 range, in whatever   */
+/* units: min-sum is the same at every scale but for the saturation).       */
+/* Check updates:                                                           */
 /*   kind 0, saturating min-sum: f = sign(a) sign(b) min(|a|, |b|)           */
 /*   kind 1, phi table:          f = sign(a) sign(b) min(T[min(T[|a|] +     */
 /*       T[|b|], len-1)], |a|, |b|), T[i] = phi(i 2^-FRAC) in the same units */
 /*       (T[i] = 0 beyond the table), the min with |a|, |b| because the     */
 /*       exact update never exceeds either magnitude (it also stands in for  */
 /*       T[0] = phi(0) = infinity)                                           */
-/* Variable update for both: g = sat(b + (1 - 2u) a).  Decisions [L < 0].    */
+/*   kind 2, saturating min-sum on 8-bit integers: f as kind 0               */
+/* Variable update for all: g = sat(b + (1 - 2u) a).  Decisions [L < 0].     */
 /* ------------------------------------------------------------------------ */
 #define FIXED_MAX 32767
+#define FIXED8_MAX 127
 
-static int32_t sat16(int32_t x) { return x > FIXED_MAX ? FIXED_MAX : (x < -FIXED_MAX ? -FIXED_MAX : x); }
+static int32_t sat_to(int32_t x, int32_t lim) { return x > lim ? lim : (x < -lim ? -lim : x); }
 
 /* T[i] = round(phi(i 2^-frac) 2^frac), phi(x) = ln(1 + 2 / expm1(x)) (the
  * same function as -ln tanh(x/2), without cancellation for large x),
@@ -354,6 +358,7 @@ typedef struct {
     uint8_t* u_hat;
     int32_t* leaf;
     int kind;
+    int32_t max;  /* saturation: FIXED_MAX, or FIXED8_MAX for kind 2 */
     const int32_t* table;
     int len;
     int32_t** alpha_lvl;
@@ -375,7 +380,7 @@ static int32_t fx_f(const fx_ctx* c, int32_t a, int32_t b) {
     return ((a < 0) != (b < 0)) ? -r : r;
 }
 
-static int32_t fx_g(int32_t a, int32_t b, int u) { return sat16(u ? b - a : b + a); }
+static int32_t fx_g(const fx_ctx* c, int32_t a, int32_t b, int u) { return sat_to(u ? b - a : b + a, c->max); }
 
 static void dec_fixed(const int32_t* alpha, int64_t m, int64_t off, int depth, fx_ctx* c, uint8_t* beta) {
     if (m == 1) {
@@ -392,7 +397,7 @@ static void dec_fixed(const int32_t* alpha, int64_t m, int64_t off, int depth, f
     uint8_t* br = c->br_lvl[depth];
     for (int64_t j = 0; j < h; ++j) a[j] = fx_f(c, alpha[j], alpha[j + h]);
     dec_fixed(a, h, off, depth + 1, c, bl);
-    for (int64_t j = 0; j < h; ++j) a[j] = fx_g(alpha[j], alpha[j + h], bl[j]);
+    for (int64_t j = 0; j < h; ++j) a[j] = fx_g(c, alpha[j], alpha[j + h], bl[j]);
     dec_fixed(a, h, off + h, depth + 1, c, br);
     for (int64_t j = 0; j < h; ++j) {
         beta[j] = (uint8_t)(bl[j] ^ br[j]);
@@ -401,18 +406,20 @@ static void dec_fixed(const int32_t* alpha, int64_t m, int64_t off, int depth, f
 }
 
 /* Decode one frame in fixed point.  llr: N integers (channel LLRs in units
- * of 2^-frac, inside +-32767); kind 0 saturating min-sum, 1 phi table
- * (table of len entries, from oracle_phi_table); leaf (nullable) receives
- * the N decision LLRs.  Returns 0 or -1. */
+ * of 2^-frac, inside +-32767, or +-127 for kind 2); kind 0 saturating
+ * min-sum, 1 phi table (table of len entries, from oracle_phi_table), 2
+ * saturating min-sum on 8-bit integers; leaf (nullable) receives the N
+ * decision LLRs.  Returns 0 or -1. */
 int oracle_sc_decode_fixed(int log2n, int kind, const int32_t* llr, const uint8_t* frozen, const uint8_t* fval,
                            const uint8_t* teacher, uint8_t* u_hat, int32_t* leaf, const int32_t* table,
                            int len) {
     if (log2n < 0 || log2n > 30 || !llr || !frozen || !fval || !u_hat) return -1;
-    if (kind != 0 && kind != 1) return -1;
+    if (kind != 0 && kind != 1 && kind != 2) return -1;
     if (kind == 1 && (!table || len < 2)) return -1;
+    const int32_t lim = kind == 2 ? FIXED8_MAX : FIXED_MAX;
     int64_t n = (int64_t)1 << log2n;
     for (int64_t j = 0; j < n; ++j)
-        if (llr[j] > FIXED_MAX || llr[j] < -FIXED_MAX) return -1;
+        if (llr[j] > lim || llr[j] < -lim) return -1;
     fx_ctx c;
     c.frozen = frozen;
     c.fval = fval;
@@ -420,6 +427,7 @@ int oracle_sc_decode_fixed(int log2n, int kind, const int32_t* llr, const uint8_
     c.u_hat = u_hat;
     c.leaf = leaf;
     c.kind = kind;
+    c.max = lim;
     c.table = table;
     c.len = len;
     c.alpha_lvl = (int32_t**)calloc((size_t)log2n + 1, sizeof(int32_t*));
@@ -588,6 +596,7 @@ int32_t oracle_f_fixed(int kind, int32_t a, int32_t b, const int32_t* table, int
     fx_ctx c;
     memset(&c, 0, sizeof c);
     c.kind = kind;
+    c.max = kind == 2 ? FIXED8_MAX : FIXED_MAX;
     c.table = table;
     c.len = len;
     return fx_f(&c, a, b);

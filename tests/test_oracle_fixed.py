@@ -10,7 +10,10 @@ phi = -ln tanh(x/2) table as the check update), no GPU.
   saturates (integer-valued FP32 min-sum is exact, so they must agree bit
   for bit);
 * the phi-table update against the FP64 exact box-plus update, converging
-  as the grid is refined."""
+  as the grid is refined;
+* the 8-bit saturating min-sum kind: the same per-bit pin, saturation at
+  +-127 by hand-built frames, and equality with the 16-bit kind where no
+  value can reach 127."""
 import math
 
 import numpy as np
@@ -39,15 +42,16 @@ def test_phi_table_against_definition():
             assert abs(int(t[j]) - i) <= max(1, i // 8), i
 
 
-@pytest.mark.parametrize("kind", [oracle.FIXED_MINSUM, oracle.FIXED_PHI])
+@pytest.mark.parametrize("kind", [oracle.FIXED_MINSUM, oracle.FIXED_PHI, oracle.FIXED_MINSUM8])
 @pytest.mark.parametrize("log2n", [1, 2, 3, 4, 5, 6])
 def test_fixed_decoder_equals_naive_per_bit(kind, log2n):
     g = np.random.default_rng(40 + 10 * kind + log2n)
     n = 1 << log2n
     table = oracle.phi_table()
+    lim = oracle.FIXED8_MAX if kind == oracle.FIXED_MINSUM8 else oracle.FIXED_MAX
     for trial in range(6):
         if trial % 3 == 0:   # near saturation: large magnitudes
-            llr = g.integers(-oracle.FIXED_MAX, oracle.FIXED_MAX + 1, n)
+            llr = g.integers(-lim, lim + 1, n)
         elif trial % 3 == 1:  # BSC-like
             llr = np.where(g.random(n) < 0.1, -62, 62)
         else:                 # small values, zeros
@@ -115,3 +119,40 @@ def test_quantize():
     q = oracle.quantize([0.03, -0.03, 1.0, -2047.99, 5000.0, -5000.0])
     assert list(q) == [0, 0, 16, -32768 + 1, 32767, -32767]
     assert list(oracle.quantize([0.0625 * 3.5, 0.0625 * 2.5])) == [4, 2]  # ties to even
+
+
+def test_int8_saturation_closed_form():
+    """8-bit kind, N = 2: inputs (100, 100), rate 1: f = 100 decided 0, and
+    g = 200 saturates to 127; (100, -100) with the first bit frozen to 1:
+    f = -100, g = -200 saturates to -127.  Inputs beyond +-127 are refused."""
+    k = oracle.FIXED_MINSUM8
+    u, leaf = oracle.sc_decode_fixed([100, 100], [0, 0], [0, 0], k, want_leaf=True)
+    assert list(leaf) == [100, 127] and list(u) == [0, 0]
+    u, leaf = oracle.sc_decode_fixed([100, -100], [1, 0], [1, 0], k, want_leaf=True)
+    assert list(leaf) == [-100, -127] and list(u) == [1, 1]
+    with pytest.raises(ValueError):
+        oracle.sc_decode_fixed([128, 0], [0, 0], [0, 0], k)
+    assert oracle.f_fixed(k, 90, -100) == -90
+
+
+@pytest.mark.parametrize("log2n", [3, 5, 6])
+def test_int8_minsum_equals_int16_minsum_without_saturation(log2n):
+    """With inputs of +-1 and N <= 64 no LLR can pass N, so nothing reaches
+    127 and the 8-bit kind must equal the 16-bit saturating min-sum; a rate-1
+    frame of 100s shows the 8-bit kind saturating where the other does not."""
+    g = np.random.default_rng(90 + log2n)
+    n = 1 << log2n
+    for k in range(6):
+        llr = np.where(g.random(n) < 0.3, -1, 1) * (k % 2)
+        frozen = (g.random(n) < [0.2, 0.5, 0.8][k % 3]).astype(np.uint8)
+        fval = (g.integers(0, 2, n) & frozen).astype(np.uint8)
+        t = g.integers(0, 2, n).astype(np.uint8)
+        u16, l16 = oracle.sc_decode_fixed(llr, frozen, fval, oracle.FIXED_MINSUM, teacher=t, want_leaf=True)
+        u8, l8 = oracle.sc_decode_fixed(llr, frozen, fval, oracle.FIXED_MINSUM8, teacher=t, want_leaf=True)
+        assert np.abs(l16).max() <= n < oracle.FIXED8_MAX
+        assert np.array_equal(u8, u16) and np.array_equal(l8, l16)
+    ones = np.full(n, 100)
+    z = np.zeros(n, np.uint8)
+    _, l16 = oracle.sc_decode_fixed(ones, z, z, oracle.FIXED_MINSUM, want_leaf=True)
+    _, l8 = oracle.sc_decode_fixed(ones, z, z, oracle.FIXED_MINSUM8, want_leaf=True)
+    assert l16[-1] == min(100 * n, oracle.FIXED_MAX) and l8[-1] == oracle.FIXED8_MAX

@@ -27,8 +27,9 @@ MUTATIONS = {
     "bhatt_children_swapped": ("bz[2 * j] = mz;", "bz[2 * j] = pz;"),
     "boxplus_log_sign": ("return s * (m + log1p(exp(-(A + B))) - log1p(exp(-fabs(A - B))));",
                          "return s * (m - log1p(exp(-(A + B))) - log1p(exp(-fabs(A - B))));"),
-    "fixed_g_unsaturated": ("static int32_t fx_g(int32_t a, int32_t b, int u) { return sat16(u ? b - a : b + a); }",
-                            "static int32_t fx_g(int32_t a, int32_t b, int u) { return u ? b - a : b + a; }"),
+    "fixed_g_unsaturated": ("return sat_to(u ? b - a : b + a, c->max); }", "return u ? b - a : b + a; }"),
+    "fixed8_saturates_at_int16": ("const int32_t lim = kind == 2 ? FIXED8_MAX : FIXED_MAX;",
+                                  "const int32_t lim = FIXED_MAX;"),
     "fixed_phi_sum_drops_term": ("int32_t s = fx_phi(c, A) + fx_phi(c, B);", "int32_t s = fx_phi(c, A);"),
     "fixed_phi_drops_min_clamp": ("r = t < m ? t : m;", "r = t;"),
     "phi_table_shifted": ("double v = log1p(2.0 / expm1(i * step)) / step;",
@@ -115,15 +116,16 @@ def _bhatt_pin_catches(lib):
 
 def _fixed_pin_catches(lib):
     """The fixed-point decoder against the per-bit naive decoder in the same
-    integer arithmetic (saturation exercised), both check updates."""
+    integer arithmetic (saturation exercised), every check update."""
     g = np.random.default_rng(12)
     table = oracle.phi_table()
     tab = np.ascontiguousarray(table, np.int32)
-    for kind in (0, 1):
+    for kind in (0, 1, 2):
+        lim = 127 if kind == 2 else 32767
         for log2n in (2, 4, 5):
             n = 1 << log2n
             for trial in range(6):
-                llr = (g.integers(-32767, 32768, n) if trial % 2 else g.integers(-90, 91, n)).astype(np.int32)
+                llr = (g.integers(-lim, lim + 1, n) if trial % 2 else g.integers(-90, 91, n)).astype(np.int32)
                 mask = (g.random(n) < 0.4).astype(np.uint8)
                 fval = (g.integers(0, 2, n) & mask).astype(np.uint8)
                 u = np.empty(n, np.uint8)
@@ -159,6 +161,7 @@ def test_planted_mistake_is_caught(tmp_path, name):
         "bhatt_children_swapped": _bhatt_pin_catches,
         "boxplus_log_sign": _boxplus_pin_catches,
         "fixed_g_unsaturated": _fixed_pin_catches,
+        "fixed8_saturates_at_int16": _fixed_pin_catches,
         "fixed_phi_sum_drops_term": _fixed_pin_catches,
         "fixed_phi_drops_min_clamp": _fixed_pin_catches,
         "phi_table_shifted": _phi_table_pin_catches,
