@@ -131,6 +131,17 @@ def mixed_frames(seed=4):
 CONFIGS["n20-bsc-x256-q16"] = dict(desc="N=2^20, BSC p=0.03, rate 0.75, 256 frames, fixed-point LLRs (2^-4), "
                                    "saturating min-sum", frames=[(20, "bsc", 0.03, 262144)] * 256, fkind=2,
                                    seed_base=2000, fixed=True)
+CONFIGS["n20-bsc-x256-q8"] = dict(desc="N=2^20, BSC p=0.03, rate 0.75, 256 frames, 8-bit LLRs (2^-2, saturated "
+                                  "to 127), saturating min-sum", frames=[(20, "bsc", 0.03, 262144)] * 256, fkind=4,
+                                  seed_base=2000, fixed=True)
+
+
+def quantize_for(cfg, llr):
+    """Channel LLRs of a fixed-point workload: integers in units of 2^-4
+    (16-bit kinds) or 2^-2 saturated to 127 (the 8-bit kind), as float32."""
+    return synth.fixed_point(llr, frac=2, limit=127) if cfg["fkind"] == 4 else synth.fixed_point(llr)
+
+
 CONFIGS["n20-bsc-x256-phi"] = dict(desc="N=2^20, BSC p=0.03, rate 0.75, 256 frames, fixed-point LLRs (2^-4), "
                                    "phi-table check update", frames=[(20, "bsc", 0.03, 262144)] * 256, fkind=3,
                                    seed_base=2000, fixed=True)
@@ -170,7 +181,7 @@ def make_inputs(cfg_name, lp, torch, dev):
 
         u, fval, llr = synth.frame(cfg["seed_base"] + k, log2n, ch, prm, mbits, gpu_encode)
         if cfg.get("fixed"):
-            llr = synth.fixed_point(llr)
+            llr = quantize_for(cfg, llr)
         items.append(dict(log2n=log2n, f_kind=cfg["fkind"], llr=torch.from_numpy(llr).to(dev),
                           frozen_mask=mdev,
                           frozen_vals=torch.from_numpy(synth.pack_bits(fval).view(np.int32).copy()).to(dev),
@@ -234,7 +245,8 @@ def oracle_frames(cfg_name, count):
         mask = masks[key]
         _, fval, llr = synth.frame(cfg["seed_base"] + k, log2n, ch, prm, mask, lambda v, n=log2n: oracle.encode(n, v))
         if cfg.get("fixed"):
-            llr = oracle.quantize(llr).astype(np.float32)
+            llr = (oracle.quantize(llr, 2, oracle.FIXED8_MAX) if cfg["fkind"] == 4 else
+                   oracle.quantize(llr)).astype(np.float32)
         out.append((llr, mask, fval))
     return out
 
@@ -250,7 +262,7 @@ def cpu_baseline(cfg_name, host, boxplus, budget_s=20.0):
     import oracle
 
     cfg = CONFIGS[cfg_name]
-    fixed_kind = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI}.get(cfg["fkind"])
+    fixed_kind = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI, 4: oracle.FIXED_MINSUM8}.get(cfg["fkind"])
 
     def one_frame(h):
         if fixed_kind is not None:
@@ -467,7 +479,8 @@ def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1,
     ranking = ("Bhattacharyya-ranked frozen set" if construction == "bhattacharyya" else
                f"frozen set ranked by the device's degrading construction, mu={mu}")
     arith = {0: "FP32 min-sum", 1: "FP32 exact box-plus", 2: "fixed-point saturating min-sum",
-             3: "fixed-point phi-table exact update"}[f_kind]
+             3: "fixed-point phi-table exact update",
+             4: "8-bit saturating min-sum (LLRs in units of 2^-2, saturated to 127)"}[f_kind]
     return dict(channel=f"BSC p={p}", capacity=round(cap, 6), target_fer=target, rule="largest K with FER <= target "
                 f"({ranking}, {arith} SC, fresh frames for the reported point)",
                 points=out, note="the paper's frozen sets come from density evolution [MT09]")
@@ -622,12 +635,13 @@ def main(argv=None):
     value = total_bits / (ms_step / 1e3) / 1e6
 
     # roofline of the decode kernel: algorithmic bytes / measured launch time
-    level_bytes = 2 if cfg["fkind"] >= 2 else 4  # the fixed-point kinds keep HBM levels as int16
+    level_bytes = {2: 2, 3: 2, 4: 1}.get(cfg["fkind"], 4)  # the fixed-point kinds keep HBM levels as int16 / int8
     alg_bytes = sum((1 << it["log2n"]) * bytes_per_bit(it["log2n"], level_bytes) for it in items)
     achieved = alg_bytes / (ev_ms / 1e3) / 1e9
     source = decoder_source_hash()
     tr = measured_traffic(args.config, source) if (cfg["fkind"] == 0 and args.prune and not args.cutover) else None
-    dtype = {0: "f32", 1: "f32", 2: "q16 (fixed point, f32 registers)", 3: "q16 (fixed point, f32 registers)"}
+    dtype = {0: "f32", 1: "f32", 2: "q16 (fixed point, f32 registers)", 3: "q16 (fixed point, f32 registers)",
+             4: "q8 (fixed point, f32 registers)"}
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None if tr is None else int(tr["bytes"]))
     if tr is not None:
@@ -639,7 +653,7 @@ def main(argv=None):
                vs_baseline=None, dtype=dtype[cfg["fkind"]], data="synthetic",
                config=dict(workload=f"{args.config}: {cfg['desc']}", frames=n,
                            bits_per_step=total_bits, info_bits_per_step=info_bits,
-                           f_kind=["minsum", "boxplus", "minsum_q16", "phi_q16"][cfg["fkind"]],
+                           f_kind=["minsum", "boxplus", "minsum_q16", "phi_q16", "minsum_q8"][cfg["fkind"]],
                            prune=bool(args.prune),
                            graph=bool(args.graph), helpers=bool(args.helpers), decoder_source=source,
                            launch=ctx.query_launch(cfg["fkind"], max(it["log2n"] for it in items), n),
@@ -707,6 +721,8 @@ def main(argv=None):
         # the paper's arithmetic (fixed-point phi table) on sets from the
         # degrading construction
         out["fer_degrade_phi"] = fer_leg(lp, torch, dev, construction="degrade", f_kind=3)
+        # 8-bit LLRs (a quarter of the bytes): what the saturation costs
+        out["fer_q8"] = fer_leg(lp, torch, dev, f_kind=4)
 
     if not args.no_serve:
         print("[bench] serving leg", file=sys.stderr, flush=True)

@@ -61,6 +61,16 @@ extern "C" {
                                 T[0] = 32767; T is 0 from index 67 on            */
 #define POLAR_FIXED_FRAC 4
 #define POLAR_FIXED_MAX 32767
+/* Saturating min-sum on 8-bit integers (the second step of Section 4's
+   fixed point): llr holds integers with |L| <= POLAR_FIXED8_MAX, stored as
+   float, in whatever units the caller quantized to (min-sum decides the same
+   at every scale but for the saturation); g saturates to +-POLAR_FIXED8_MAX.
+   Results are bit-exact against integer arithmetic; other llr values give
+   undefined results (the decoder keeps its large LLR levels as 8-bit
+   integers). */
+#define POLAR_F_MINSUM_Q8 4
+#define POLAR_FIXED8_MAX 127
+#define POLAR_FIXED8_FRAC 2  /* units of the FER generator's 8-bit LLRs */
 
 #define POLAR_MAX_LOG2N 24
 
@@ -178,9 +188,10 @@ int polar_encode(int log2n, int n_frames, const uint32_t* u, uint32_t* x, void* 
    aligned, the other buffers 4-byte aligned. */
 typedef struct polar_frame {
     int32_t log2n;                /* 1 .. POLAR_MAX_LOG2N                              */
-    int32_t f_kind;               /* POLAR_F_MINSUM, _BOXPLUS, _MINSUM_Q16 or _PHI_Q16  */
+    int32_t f_kind;               /* POLAR_F_MINSUM, _BOXPLUS, _MINSUM_Q16, _PHI_Q16 or
+                                     _MINSUM_Q8                                        */
     const float* llr;             /* N channel LLRs, 16-byte aligned (fixed-point
-                                     kinds: integers in units of 2^-4, see above)    */
+                                     kinds: integers, see above)                      */
     const uint32_t* frozen_mask;  /* max(1, N/32) words, 1 = frozen; may be shared      */
     const uint32_t* frozen_vals;  /* max(1, N/32) words, revealed values of u_F;
                                      bits outside the mask are ignored                 */
@@ -417,8 +428,10 @@ int polar_serve(polar_ctx* ctx, const polar_serve_cfg* cfg, polar_next_fn next, 
  *   channel error, bit i = Philox((i >> 2, 1, 0, 0), key)[i & 3] < floor(p 2^32)
  *   x = u G_N; L_i = +L0 where x_i equals the error bit, else -L0, with
  *   L0 = ln((1 - p) / p) computed in double and rounded once to float32
- *   (fixed_point != 0, and the fixed-point f_kinds of polar_fer_bsc: L0 in
- *   units of 2^-POLAR_FIXED_FRAC, rounded half to even)
+ *   (fixed_point = 1, and the 16-bit fixed-point f_kinds of polar_fer_bsc: L0
+ *   in units of 2^-POLAR_FIXED_FRAC, rounded half to even; fixed_point = 2,
+ *   and POLAR_F_MINSUM_Q8: in units of 2^-POLAR_FIXED8_FRAC, rounded half to
+ *   even and capped at POLAR_FIXED8_MAX)
  *   frozen values = u on the frozen set
  * A frame is in error when its u-hat differs from u in any position.
  *

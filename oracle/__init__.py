@@ -201,11 +201,11 @@ def phi_table(frac: int = FIXED_FRAC, length: int = FIXED_TABLE_LEN) -> np.ndarr
     return out
 
 
-def quantize(llr, frac: int = FIXED_FRAC) -> np.ndarray:
+def quantize(llr, frac: int = FIXED_FRAC, limit: int = FIXED_MAX) -> np.ndarray:
     """Channel LLRs to fixed point: round(L 2^frac) (round half to even),
-    saturated to +-FIXED_MAX."""
+    saturated to +-limit."""
     q = np.round(np.asarray(llr, np.float64) * (1 << frac))
-    return np.clip(q, -FIXED_MAX, FIXED_MAX).astype(np.int32)
+    return np.clip(q, -limit, limit).astype(np.int32)
 
 
 def sc_decode_fixed(llr_q, frozen, fval, kind: int = FIXED_MINSUM, teacher=None, want_leaf: bool = False,

@@ -84,9 +84,10 @@ def bsc_l0(p: float) -> np.float32:
     return np.float32(math.log((1.0 - p) / p))
 
 
-def bsc_frame(seed: int, frame: int, log2n: int, p: float, mask: np.ndarray, fixed_point: bool = False):
+def bsc_frame(seed: int, frame: int, log2n: int, p: float, mask: np.ndarray, fixed_point: int = 0):
     """(u bits, frozen values, LLRs float32, channel error bits) of frame f;
-    fixed_point: LLRs in units of 2^-4 (the fixed-point decoders' input)."""
+    fixed_point 1 (or True): LLRs in units of 2^-4 (the 16-bit fixed-point
+    decoders' input); 2: in units of 2^-2 capped at 127 (the 8-bit kind's)."""
     n = 1 << log2n
     key = (seed & MASK32, frame & MASK32)
     words = _stream(0, max(1, n // 32), key)
@@ -94,7 +95,10 @@ def bsc_frame(seed: int, frame: int, log2n: int, p: float, mask: np.ndarray, fix
     e = (_stream(1, n, key) < np.uint32(bsc_threshold(p))).astype(np.uint8)
     x = oracle.encode(log2n, u)
     y = x ^ e
-    l0 = bsc_l0(p) if not fixed_point else np.float32(oracle.quantize([math.log((1.0 - p) / p)])[0])
+    l0d = math.log((1.0 - p) / p)
+    l0 = (bsc_l0(p) if not fixed_point else
+          np.float32(oracle.quantize([l0d], 2, oracle.FIXED8_MAX)[0]) if int(fixed_point) == 2 else
+          np.float32(oracle.quantize([l0d])[0]))
     llr = np.where(y == 1, -l0, l0).astype(np.float32)
     fval = (u & mask).astype(np.uint8)
     return u, fval, llr, e
@@ -117,7 +121,8 @@ def fer_bsc(seed: int, frame0: int, n_frames: int, log2n: int, p: float, mask: n
     import os
 
     def one(f):
-        u, fval, llr, _ = bsc_frame(seed, frame0 + f, log2n, p, mask, fixed_point=fixed_kind is not None)
+        fixed = 0 if fixed_kind is None else (2 if fixed_kind == oracle.FIXED_MINSUM8 else 1)
+        u, fval, llr, _ = bsc_frame(seed, frame0 + f, log2n, p, mask, fixed_point=fixed)
         if fixed_kind is not None:
             uh = oracle.sc_decode_fixed(llr.astype(np.int32), mask, fval, fixed_kind)[0]
         else:

@@ -53,6 +53,9 @@ struct LaunchCfg {
     int helpers = 0;      // sweep helpers beside the frame workgroups (computed, not tuned)
 };
 
+// Launch-group keys: f_kind * 2 + leaf dump, for every check-update kind.
+constexpr int kGroupKeys = (POLAR_F_MINSUM_Q8 + 1) * 2;
+
 // Frame sizes of one launch group: count per log2 N.
 struct SizeHist {
     int n[POLAR_MAX_LOG2N + 1] = {};
@@ -124,7 +127,7 @@ struct polar_ctx {
     polar_host::Stager stager;
     // resident workgroups per compute unit, per decoder variant and size
     // (fixed size, filled on first use: lookups never allocate)
-    mutable std::vector<int> occ_cache = std::vector<int>(5 * 4 * 2 * 2 * 26 * 8, 0);
+    mutable std::vector<int> occ_cache = std::vector<int>(5 * 5 * 2 * 2 * 26 * 8, 0);
     // autotuned launch configurations, key (f_kind, log2n of the largest frame)
     std::map<std::pair<int, int>, polar_host::LaunchCfg> tuned;
     // allocation-free decoding (polar_sc_decode_batch_static): host tables

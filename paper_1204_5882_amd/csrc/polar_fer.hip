@@ -12,7 +12,8 @@
 //   u word w            = Philox((w >> 2, 0, 0, 0), key)[w & 3]
 //   channel error, bit i = Philox((i >> 2, 1, 0, 0), key)[i & 3] < floor(p 2^32)
 //   x = u G_N, L_i = +L0 if x_i = e_i else -L0, L0 = float32(ln((1 - p)/p))
-//   (fixed-point check updates: L0 in units of 2^-4, rounded half to even)
+//   (16-bit fixed-point check updates: L0 in units of 2^-4, rounded half to
+//   even; the 8-bit kind: in units of 2^-2, rounded half to even, capped at 127)
 //   frozen values = u on the frozen set
 // A frame is in error when its u-hat differs from u anywhere.
 #include <hip/hip_runtime.h>
@@ -165,7 +166,7 @@ int check_cfg(const polar_fer_cfg* cfg) {
     if (!cfg) return fail(POLAR_E_INVAL, "cfg is NULL");
     if (cfg->log2n < 1 || cfg->log2n > POLAR_MAX_LOG2N)
         return fail(POLAR_E_INVAL, "log2n %d outside 1..%d", cfg->log2n, POLAR_MAX_LOG2N);
-    if (cfg->f_kind < POLAR_F_MINSUM || cfg->f_kind > POLAR_F_PHI_Q16) return fail(POLAR_E_INVAL, "unknown f_kind");
+    if (cfg->f_kind < POLAR_F_MINSUM || cfg->f_kind > POLAR_F_MINSUM_Q8) return fail(POLAR_E_INVAL, "unknown f_kind");
     if (!(cfg->p > 0.0 && cfg->p < 0.5)) return fail(POLAR_E_INVAL, "p must lie in (0, 1/2)");
     if (!cfg->frozen_mask) return fail(POLAR_E_INVAL, "frozen_mask is NULL");
     if (cfg->n_frames < 0 || cfg->frame0 < 0 || cfg->frame0 + cfg->n_frames > ((int64_t)1 << 32))
@@ -221,6 +222,7 @@ extern "C" int polar_fer_generate_bsc(int log2n, double p, int fixed_point, cons
                                       uint32_t* frozen_vals, uint32_t* x_scratch, float* llr, void* stream) {
     if (log2n < 1 || log2n > POLAR_MAX_LOG2N) return fail(POLAR_E_INVAL, "log2n %d outside 1..%d", log2n, POLAR_MAX_LOG2N);
     if (!(p > 0.0 && p < 0.5)) return fail(POLAR_E_INVAL, "p must lie in (0, 1/2)");
+    if (fixed_point < 0 || fixed_point > 2) return fail(POLAR_E_INVAL, "fixed_point must be 0, 1 or 2");
     if (n_frames < 0 || frame0 < 0 || frame0 + n_frames > ((int64_t)1 << 32))
         return fail(POLAR_E_INVAL, "frame indices must lie in 0 .. 2^32 - 1");
     if (n_frames == 0) return ok();
@@ -230,10 +232,12 @@ extern "C" int polar_fer_generate_bsc(int log2n, double p, int fixed_point, cons
     const int64_t wpf = wpf_of(log2n);
     const int64_t n = (int64_t)1 << log2n;
     const uint32_t th = (uint32_t)std::floor(p * 4294967296.0);
-    // fixed point: L0 in units of 2^-4, rounded half to even, saturated
+    // fixed point: L0 in units of 2^-4 (8-bit: 2^-2), rounded half to even, saturated
     const double l0d = std::log((1.0 - p) / p);
-    const float l0 = fixed_point ? (float)std::min(std::nearbyint(l0d * (1 << POLAR_FIXED_FRAC)), (double)POLAR_FIXED_MAX)
-                                 : (float)l0d;
+    const float l0 = fixed_point == 1 ? (float)std::min(std::nearbyint(l0d * (1 << POLAR_FIXED_FRAC)), (double)POLAR_FIXED_MAX)
+                     : fixed_point == 2
+                         ? (float)std::min(std::nearbyint(l0d * (1 << POLAR_FIXED8_FRAC)), (double)POLAR_FIXED8_MAX)
+                         : (float)l0d;
     hipLaunchKernelGGL(k_gen_u, dim3(grid_of((wpf + 3) / 4 * n_frames)), dim3(256), 0, s, (uint32_t)seed,
                        (uint32_t)frame0, n_frames, log2n, wpf, frozen_mask, u, frozen_vals);
     hipError_t e = polar_dev_encode(log2n, n_frames, u, x_scratch, s);
@@ -280,7 +284,8 @@ extern "C" int polar_fer_bsc(polar_ctx* c, const polar_fer_cfg* cfg, void* works
     Plan p;
     for (int64_t done = 0; done < cfg->n_frames; done += L.batch) {
         const int nb = (int)std::min<int64_t>(L.batch, cfg->n_frames - done);
-        rc = polar_fer_generate_bsc(log2n, cfg->p, cfg->f_kind >= POLAR_F_MINSUM_Q16, cfg->frozen_mask, cfg->seed,
+        const int fixed = cfg->f_kind == POLAR_F_MINSUM_Q8 ? 2 : (cfg->f_kind >= POLAR_F_MINSUM_Q16 ? 1 : 0);
+        rc = polar_fer_generate_bsc(log2n, cfg->p, fixed, cfg->frozen_mask, cfg->seed,
                                     cfg->frame0 + done, nb, u, vals, x, llr, stream);
         if (rc) return rc;
         fr.assign((size_t)nb, polar_frame{});

@@ -260,7 +260,7 @@ int validate_frames(const polar_frame* frames, int n_frames) {
         const polar_frame& f = frames[i];
         if (f.log2n < 1 || f.log2n > POLAR_MAX_LOG2N)
             return fail(POLAR_E_INVAL, "frame %d: log2n %d outside 1..%d", i, f.log2n, POLAR_MAX_LOG2N);
-        if (f.f_kind < POLAR_F_MINSUM || f.f_kind > POLAR_F_PHI_Q16)
+        if (f.f_kind < POLAR_F_MINSUM || f.f_kind > POLAR_F_MINSUM_Q8)
             return fail(POLAR_E_INVAL, "frame %d: unknown f_kind %d", i, f.f_kind);
         if (!f.llr || !f.frozen_mask || !f.frozen_vals || !f.u_hat)
             return fail(POLAR_E_INVAL, "frame %d: NULL buffer", i);
@@ -273,8 +273,8 @@ int validate_frames(const polar_frame* frames, int n_frames) {
 }
 
 int occupancy(const polar_ctx* c, int cutover, int fk, bool dump, int waves, bool prune, int small_log2n) {
-    // cache slot: cutover 8..12, f_kind 0..3, dump, prune, small_log2n -1..24, waves 1..8
-    const int key = (((((cutover - 8) * 4 + fk) * 2 + (dump ? 1 : 0)) * 2 + (prune ? 1 : 0)) * 26 + small_log2n + 1) *
+    // cache slot: cutover 8..12, f_kind 0..4, dump, prune, small_log2n -1..24, waves 1..8
+    const int key = (((((cutover - 8) * 5 + fk) * 2 + (dump ? 1 : 0)) * 2 + (prune ? 1 : 0)) * 26 + small_log2n + 1) *
                         8 + (waves - 1);
     const bool cacheable = cutover >= 8 && cutover <= 12 && waves >= 1 && waves <= 8 && small_log2n >= -1 &&
                            small_log2n <= POLAR_MAX_LOG2N && key >= 0 && key < (int)c->occ_cache.size();
@@ -375,13 +375,14 @@ void make_plan(const polar_ctx* c, const polar_frame* frames, int n_frames, bool
                const LaunchCfg* force, bool per_frame) {
     // order: by (f_kind, leaf dump), inside a group most work (largest N)
     // first, ties in submission order: a stable counting sort over the
-    // 8 x 25 keys (no allocation once the plan's vectors have the capacity)
+    // kGroupKeys x 25 keys (no allocation once the plan's vectors have the
+    // capacity)
     constexpr int NL = POLAR_MAX_LOG2N + 1;
     auto key = [&](int i) { return frames[i].f_kind * 2 + (frames[i].leaf_llr ? 1 : 0); };
     auto bucket = [&](int i) { return key(i) * NL + (POLAR_MAX_LOG2N - frames[i].log2n); };
-    int start[8 * NL + 1] = {};
+    int start[kGroupKeys * NL + 1] = {};
     for (int i = 0; i < n_frames; ++i) ++start[bucket(i) + 1];
-    for (int b = 0; b < 8 * NL; ++b) start[b + 1] += start[b];
+    for (int b = 0; b < kGroupKeys * NL; ++b) start[b + 1] += start[b];
     std::vector<int>& order = p.order;
     order.resize((size_t)n_frames);
     for (int i = 0; i < n_frames; ++i) order[(size_t)start[bucket(i)]++] = i;

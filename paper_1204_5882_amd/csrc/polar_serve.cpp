@@ -103,12 +103,12 @@ bool arena_find(const polar_server* s, size_t need, size_t* off) {
 // make_plan computes, kept per launch group so that adding a frame costs no
 // re-planning.
 struct BatchSize {
-    SizeHist g[8];  // f_kind * 2 + leaf dump
+    SizeHist g[kGroupKeys];  // f_kind * 2 + leaf dump
     int n = 0;
     static int key(const polar_frame& f) { return f.f_kind * 2 + (f.leaf_llr ? 1 : 0); }
     size_t total(const polar_ctx* c, const SizeHist* h, int nf) const {
         int64_t slots = 0;
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < kGroupKeys; ++k) {
             if (!h[k].count) continue;
             const LaunchCfg cfg = group_cfg(c, k >> 1, (k & 1) != 0, h[k], false, nullptr, false);
             slots += group_slot_bytes(h[k], cfg, true, nullptr);
@@ -116,8 +116,8 @@ struct BatchSize {
         return align256(256 + sizeof(FrameDesc) * (size_t)nf) + (size_t)slots;
     }
     size_t total_with(const polar_ctx* c, const polar_frame& f) const {
-        SizeHist h[8];
-        for (int k = 0; k < 8; ++k) h[k] = g[k];
+        SizeHist h[kGroupKeys];
+        for (int k = 0; k < kGroupKeys; ++k) h[k] = g[k];
         h[key(f)].add(f.log2n);
         return total(c, h, n + 1);
     }

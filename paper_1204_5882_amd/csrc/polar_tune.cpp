@@ -160,7 +160,7 @@ extern "C" int polar_query_launch(const polar_ctx* c, int f_kind, int log2n, int
                                   int* waves, int* slots, int* fwg, int* prune) {
     if (!c) return fail(POLAR_E_INVAL, "ctx is NULL");
     if (log2n < 1 || log2n > POLAR_MAX_LOG2N) return fail(POLAR_E_INVAL, "log2n %d outside 1..%d", log2n, POLAR_MAX_LOG2N);
-    if (f_kind < POLAR_F_MINSUM || f_kind > POLAR_F_PHI_Q16) return fail(POLAR_E_INVAL, "unknown f_kind");
+    if (f_kind < POLAR_F_MINSUM || f_kind > POLAR_F_MINSUM_Q8) return fail(POLAR_E_INVAL, "unknown f_kind");
     if (n_frames < 1) return fail(POLAR_E_INVAL, "n_frames < 1");
     SizeHist h;
     for (int i = 0; i < n_frames; ++i) h.add(log2n);
@@ -241,7 +241,7 @@ extern "C" int polar_tune_load(polar_ctx* c, const char* path) {
             return fail(POLAR_E_INVAL, "%s: entry lacks a field", path);
         (void)read_int(obj, "fwg", &fw);    // optional
         (void)read_int(obj, "prune", &pr);  // optional
-        if (fk < POLAR_F_MINSUM || fk > POLAR_F_PHI_Q16 || lg < 1 || lg > POLAR_MAX_LOG2N ||
+        if (fk < POLAR_F_MINSUM || fk > POLAR_F_MINSUM_Q8 || lg < 1 || lg > POLAR_MAX_LOG2N ||
             !polar_dev_cutover_supported((int)cut) || !polar_dev_waves_supported((int)w) || sl < 1 ||
             sl > (1 << 20) || fw < 0 || fw > w || pr < -1 || pr > 1 || (pr == 0 && cut != 12))
             return fail(POLAR_E_INVAL, "%s: entry out of range", path);

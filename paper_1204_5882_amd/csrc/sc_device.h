@@ -82,6 +82,10 @@ hipError_t polar_dec_c12_q16(const DecodeLaunch* a);
 hipError_t polar_dec_c12_q16_dump(const DecodeLaunch* a);
 hipError_t polar_dec_c12_q16_prune(const DecodeLaunch* a);
 hipError_t polar_dec_c12_q16_prune_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_q8(const DecodeLaunch* a);
+hipError_t polar_dec_c12_q8_dump(const DecodeLaunch* a);
+hipError_t polar_dec_c12_q8_prune(const DecodeLaunch* a);
+hipError_t polar_dec_c12_q8_prune_dump(const DecodeLaunch* a);
 hipError_t polar_dec_c8_bp_prune(const DecodeLaunch* a);
 hipError_t polar_dec_c8_ms_prune(const DecodeLaunch* a);
 hipError_t polar_dec_c9_bp_prune(const DecodeLaunch* a);
@@ -106,6 +110,10 @@ int polar_dec_c12_q16_occupancy(int waves, int small_log2n);
 int polar_dec_c12_q16_dump_occupancy(int waves, int small_log2n);
 int polar_dec_c12_q16_prune_occupancy(int waves, int small_log2n);
 int polar_dec_c12_q16_prune_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_q8_occupancy(int waves, int small_log2n);
+int polar_dec_c12_q8_dump_occupancy(int waves, int small_log2n);
+int polar_dec_c12_q8_prune_occupancy(int waves, int small_log2n);
+int polar_dec_c12_q8_prune_dump_occupancy(int waves, int small_log2n);
 int polar_dec_c8_bp_prune_occupancy(int waves, int small_log2n);
 int polar_dec_c8_ms_prune_occupancy(int waves, int small_log2n);
 int polar_dec_c9_bp_prune_occupancy(int waves, int small_log2n);

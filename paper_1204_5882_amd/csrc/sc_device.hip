@@ -128,6 +128,10 @@ constexpr Variant kVariants[] = {
     {12, 2, 0, 1, polar_dec_c12_q16_dump, polar_dec_c12_q16_dump_occupancy},
     {12, 2, 1, 0, polar_dec_c12_q16_prune, polar_dec_c12_q16_prune_occupancy},
     {12, 2, 1, 1, polar_dec_c12_q16_prune_dump, polar_dec_c12_q16_prune_dump_occupancy},
+    {12, 4, 0, 0, polar_dec_c12_q8, polar_dec_c12_q8_occupancy},
+    {12, 4, 0, 1, polar_dec_c12_q8_dump, polar_dec_c12_q8_dump_occupancy},
+    {12, 4, 1, 0, polar_dec_c12_q8_prune, polar_dec_c12_q8_prune_occupancy},
+    {12, 4, 1, 1, polar_dec_c12_q8_prune_dump, polar_dec_c12_q8_prune_dump_occupancy},
     {8, 1, 1, 0, polar_dec_c8_bp_prune, polar_dec_c8_bp_prune_occupancy},
     {8, 0, 1, 0, polar_dec_c8_ms_prune, polar_dec_c8_ms_prune_occupancy},
     {9, 1, 1, 0, polar_dec_c9_bp_prune, polar_dec_c9_bp_prune_occupancy},

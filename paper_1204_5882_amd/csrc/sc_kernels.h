@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sc_device.h"
 
 namespace polar_dev {
@@ -251,6 +253,18 @@ __device__ __forceinline__ float f_boxplus(float a, float b) {
 constexpr float FIXED_MAX = 32767.0f;
 constexpr int PHI_LEN = 256;
 
+// FK = 4, saturating min-sum on 8-bit integers: f as FK = 2, g saturated to
+// +-127 (values in whatever units the caller quantized to: min-sum is the same
+// at every scale but for the saturation).
+constexpr float FIXED8_MAX = 127.0f;
+
+// Kinds whose check update is min-sum (FP32, and both saturating kinds).
+template <int FK>
+constexpr bool minsum_kind() { return FK == 0 || FK == 2 || FK == 4; }
+
+template <int FK>
+constexpr float fixed_max() { return FK == 4 ? FIXED8_MAX : FIXED_MAX; }
+
 // The workgroup's copy of T (kernels with FK = 3 only: LDS is allocated only
 // in kernels that use it).
 static __shared__ float g_phi[PHI_LEN];
@@ -282,7 +296,7 @@ __device__ __forceinline__ float f_phi(float a, float b) {
 
 template <int FK>
 __device__ __forceinline__ float fupd(float a, float b) {
-    if constexpr (FK == 0 || FK == 2) return f_minsum(a, b);
+    if constexpr (minsum_kind<FK>()) return f_minsum(a, b);
     else if constexpr (FK == 1) return f_boxplus(a, b);
     else return f_phi(a, b);
 }
@@ -290,7 +304,7 @@ __device__ __forceinline__ float fupd(float a, float b) {
 // The variable update's sum, saturated for the fixed-point kinds.
 template <int FK>
 __device__ __forceinline__ float gsat(float x) {
-    if constexpr (FK >= 2) return __builtin_amdgcn_fmed3f(x, -FIXED_MAX, FIXED_MAX);
+    if constexpr (FK >= 2) return __builtin_amdgcn_fmed3f(x, -fixed_max<FK>(), fixed_max<FK>());
     else return x;
 }
 
@@ -313,8 +327,8 @@ __device__ __forceinline__ float gupd(float a, float b, uint32_t sgn) {
 //            node of size 2^L at or above 1.
 // Below the floor the decoder descends into the node like any other, which
 // is SC by construction; its children are checked again.
-//   saturating min-sum (FK = 2): as min-sum (a saturated sum of two terms of
-//            the sign of b keeps that sign and is nonzero);
+//   saturating min-sum (FK = 2, 4): as min-sum (a saturated sum of two terms
+//            of the sign of b keeps that sign and is nonzero);
 //   phi table (FK = 3): the update can round a nonzero result to 0 (f of
 //            1 and -1 is -0), but T[i] = 0 for every i >= 67 (phi(67/16) 16
 //            = 0.486 rounds to 0), so for |a|, |b| >= 67 the sum of lookups
@@ -324,7 +338,7 @@ __device__ __forceinline__ float gupd(float a, float b, uint32_t sgn) {
 //            the least bound closed under f: T[T[66] + T[66]] = T[2] = 44.
 template <int FK>
 __host__ __device__ constexpr float rate1_floor(int L) {
-    return (FK == 0 || FK == 2) ? 0.0f
+    return minsum_kind<FK>()    ? 0.0f
            : FK == 1            ? 1.0f + 0.69314718f * (float)L + 0.01f
                                 : 66.0f;
 }
@@ -480,7 +494,7 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
             B.has_leaf = true;
         }
         return dec_sign(a);
-    } else if constexpr (P == 0 && (FK == 0 || FK == 2) && M > 2) {
+    } else if constexpr (P == 0 && minsum_kind<FK>() && M > 2) {
         // (a 2-leaf rate-1 node is cheaper as plain f, g and two decisions
         // in vector registers than as two ballots and a scalar round trip)
         static_assert(M <= 32, "three-state words are 32 bits");
@@ -625,7 +639,7 @@ template <int M, int FK, bool PRUNE, bool DUMP>
 __device__ __forceinline__ void blk_node(float a, int O, Blk& B) {
     // (64-leaf cases only for min-sum without the leaf dump: with box-plus's
     // longer f, or the dump, they exceed the register budget)
-    if constexpr (PRUNE && M == 64 && (FK == 0 || FK == 2) && !DUMP) {
+    if constexpr (PRUNE && M == 64 && minsum_kind<FK>() && !DUMP) {
         uint32_t bn;
         bool known = true;
         switch (B.F) {
@@ -993,20 +1007,26 @@ __device__ __forceinline__ int64_t row_here(int wave) {
 __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
 
 // Level storage.  The FP32 kinds keep every level as float.  The fixed-point
-// kinds keep the levels that live in HBM as int16, which is exact (every
-// value is an integer within +-32767) and halves the bytes of the sweeps that
-// HBM bounds; the channel input and the LDS levels stay float.  (A zero loses
-// its sign in int16, which no decision or later update depends on: decisions
-// test L < 0, f and g give zeros of equal magnitude either way.)
+// kinds keep the levels that live in HBM as int16 (int8 for the 8-bit kind),
+// which is exact (every value is an integer within the kind's saturation) and
+// halves (quarters) the bytes of the sweeps that HBM bounds; the channel input
+// and the LDS levels stay float.  (A zero loses its sign in an integer, which
+// no decision or later update depends on: decisions test L < 0, f and g give
+// zeros of equal magnitude either way.)
 // Raw loads (4 elements: a float4, or 4 int16 in an int2) and their
 // conversion to float, kept apart so that a sweep converts only where it uses
 // the values and holds the narrow form while its loads are in flight.
 __device__ __forceinline__ float4 ldraw(const float* p) { return ld4(p); }
 __device__ __forceinline__ int2 ldraw(const int16_t* p) { return *reinterpret_cast<const int2*>(p); }
+__device__ __forceinline__ uint32_t ldraw(const int8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
 __device__ __forceinline__ float4 cvt4(float4 v) { return v; }
 __device__ __forceinline__ float4 cvt4(int2 w) {
     return make_float4((float)(((int32_t)((uint32_t)w.x << 16)) >> 16), (float)(w.x >> 16),
                        (float)(((int32_t)((uint32_t)w.y << 16)) >> 16), (float)(w.y >> 16));
+}
+__device__ __forceinline__ float4 cvt4(uint32_t w) {
+    return make_float4((float)((int32_t)(w << 24) >> 24), (float)((int32_t)(w << 16) >> 24),
+                       (float)((int32_t)(w << 8) >> 24), (float)((int32_t)w >> 24));
 }
 template <typename T>
 __device__ __forceinline__ float4 ldv(const T* p) { return cvt4(ldraw(p)); }
@@ -1016,9 +1036,18 @@ __device__ __forceinline__ void stv(int16_t* p, float4 v) {
     const uint32_t c = (uint32_t)(int32_t)v.z & 0xffffu, d = (uint32_t)(int32_t)v.w;
     *reinterpret_cast<int2*>(p) = make_int2((int32_t)(a | (b << 16)), (int32_t)(c | (d << 16)));
 }
+__device__ __forceinline__ void stv(int8_t* p, float4 v) {
+    const uint32_t a = (uint32_t)(int32_t)v.x & 0xffu, b = (uint32_t)(int32_t)v.y & 0xffu;
+    const uint32_t c = (uint32_t)(int32_t)v.z & 0xffu, d = (uint32_t)(int32_t)v.w;
+    *reinterpret_cast<uint32_t*>(p) = a | (b << 8) | (c << 16) | (d << 24);
+}
+
+// Element type of the fixed-point kinds' HBM levels.
+template <int FK>
+using narrow_t = typename std::conditional<FK == 4, int8_t, int16_t>::type;
 
 // Element types of a two-level sweep's input, middle and output levels, one
-// bit each (set: int16): LV_IN, LV_MID, LV_OUT.
+// bit each (set: the kind's integer type): LV_IN, LV_MID, LV_OUT.
 enum : uint32_t { LV_IN = 1u, LV_MID = 2u, LV_OUT = 4u };
 
 template <int FK>
@@ -1100,9 +1129,10 @@ __device__ __forceinline__ void sweep_g(const float* __restrict__ in, int64_t ha
 template <int C, int FK, bool G, typename TI = float, typename TM = float, typename TO = float>
 __device__ __forceinline__ void sweep2(const TI* __restrict__ in, int64_t h, const uint64_t* __restrict__ beta,
                                        TM* __restrict__ mid, TO* __restrict__ out, int wave, int nw) {
-    // rows in flight: int16 input moves half the bytes per row, so twice the
-    // rows keep the same bytes (and registers) in flight
-    constexpr int U = SWEEP_UNROLL / 4 * (sizeof(TI) == 2 ? 2 : 1);
+    // rows in flight: a narrow input moves fewer bytes per row, so more rows
+    // keep more of its bytes in flight (twice the rows at most: four times
+    // made the 8-bit kernels spill)
+    constexpr int U = SWEEP_UNROLL / 4 * (sizeof(TI) < 4 ? 2 : 1);
     const int l4 = lane_id_here() * 4;
     const int64_t q = h >> 1;
     const int64_t rows = q >> 8;
@@ -1149,7 +1179,7 @@ template <int C, int FK, bool G>
 __device__ __forceinline__ void sweep2_lv(uint32_t types, const float* in, int64_t h, const uint64_t* beta, float* mid,
                                           float* out, int wave, int nw) {
     if constexpr (FK >= 2) {
-        using I = int16_t;
+        using I = narrow_t<FK>;
         switch (types) {
             case LV_IN | LV_MID | LV_OUT:
                 sweep2<C, FK, G, I, I, I>((const I*)in, h, beta, (I*)mid, (I*)out, wave, nw);
@@ -1251,7 +1281,7 @@ struct CoopState {
 // decode their frames alone.
 template <int C, int FK, bool PRUNE, bool DUMP>
 constexpr bool coop_variant() {
-    return !(C == 12 && PRUNE && !DUMP && (FK == 0 || FK == 2));
+    return !(C == 12 && PRUNE && !DUMP && minsum_kind<FK>());
 }
 
 // sweep2 over the whole workgroup, shared with helpers when it is large and

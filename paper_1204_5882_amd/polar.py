@@ -29,8 +29,11 @@ POLAR_F_MINSUM = 0
 POLAR_F_BOXPLUS = 1
 POLAR_F_MINSUM_Q16 = 2
 POLAR_F_PHI_Q16 = 3
+POLAR_F_MINSUM_Q8 = 4
 POLAR_FIXED_FRAC = 4
 POLAR_FIXED_MAX = 32767
+POLAR_FIXED8_MAX = 127
+POLAR_FIXED8_FRAC = 2
 POLAR_MAX_LOG2N = 24
 
 POLAR_OPT_PRUNE = 1
@@ -278,11 +281,13 @@ def encode(log2n: int, u, x=None, n_frames: Optional[int] = None, stream=None):
     return x
 
 
-def fer_generate_bsc(log2n: int, p: float, frozen_mask, seed: int, frame0: int, n_frames: int, fixed_point=False,
+def fer_generate_bsc(log2n: int, p: float, frozen_mask, seed: int, frame0: int, n_frames: int, fixed_point=0,
                      stream=None):
     """Synthetic BSC frames on the device (the harness's generator): returns
     (u words, frozen-value words, LLRs) as torch tensors of shapes
-    (n_frames, W), (n_frames, W), (n_frames, N)."""
+    (n_frames, W), (n_frames, W), (n_frames, N).  fixed_point: 0 FP32 LLRs,
+    1 (or True) integers in units of 2^-4, 2 integers in units of 2^-2
+    capped at 127 (the 8-bit kind)."""
     import torch
 
     dev = frozen_mask.device
@@ -291,7 +296,7 @@ def fer_generate_bsc(log2n: int, p: float, frozen_mask, seed: int, frame0: int, 
     vals = torch.empty_like(u)
     x = torch.empty_like(u)
     llr = torch.empty((n_frames, 1 << log2n), dtype=torch.float32, device=dev)
-    _check(load().polar_fer_generate_bsc(int(log2n), float(p), int(bool(fixed_point)), _ptr(frozen_mask),
+    _check(load().polar_fer_generate_bsc(int(log2n), float(p), int(fixed_point), _ptr(frozen_mask),
                                          int(seed), int(frame0),
                                          int(n_frames), _ptr(u), _ptr(vals), _ptr(x), _ptr(llr),
                                          _stream_handle(stream)))

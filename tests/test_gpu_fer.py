@@ -89,22 +89,24 @@ def test_device_fer_equals_oracle_fer(log2n, p, nf, frames, frame0):
     ctx.close()
 
 
-@pytest.mark.parametrize("fk", [2, 3])
+@pytest.mark.parametrize("fk", [2, 3, 4])
 def test_device_fer_fixed_point_equals_oracle(fk):
-    """The harness with the fixed-point decoders (LLRs +-round(16 L0)):
-    the same per-frame errors as the oracle's integer decoder."""
+    """The harness with the fixed-point decoders (LLRs +-round(16 L0), or
+    +-round(4 L0) for the 8-bit kind): the same per-frame errors as the
+    oracle's integer decoder."""
     import torch
 
     from paper_1204_5882_amd import polar as lp
 
     log2n, p, nf, frames = 11, 0.03, 600, 500
-    kind = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI}[fk]
+    kind = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI, 4: oracle.FIXED_MINSUM8}[fk]
+    fixed = 2 if fk == 4 else 1
     mask, _, _ = oracle.frozen_set(log2n, synth.bsc_z0(p), nf)
     _say(f"case: fixed-point generator and FER, f_kind={fk}")
-    u, vals, llr = lp.fer_generate_bsc(log2n, p, _mask_dev(mask), seed=9, frame0=0, n_frames=2, fixed_point=True)
+    u, vals, llr = lp.fer_generate_bsc(log2n, p, _mask_dev(mask), seed=9, frame0=0, n_frames=2, fixed_point=fixed)
     torch.cuda.synchronize()
     for k in range(2):
-        _, _, ollr, _ = fer.bsc_frame(9, k, log2n, p, mask, fixed_point=True)
+        _, _, ollr, _ = fer.bsc_frame(9, k, log2n, p, mask, fixed_point=fixed)
         assert np.array_equal(llr.cpu().numpy()[k], ollr)
     ctx = lp.Ctx(0)
     res, bit_err = ctx.fer_bsc(log2n, p, _mask_dev(mask), frames, seed=9, f_kind=fk)

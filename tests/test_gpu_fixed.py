@@ -1,9 +1,10 @@
 """GPU parity of the fixed-point decoders (Section 4's arithmetic: fixed-point
 LLRs, check update from a phi = -ln tanh(x/2) table) against the oracle's
 integer implementation: u-hat and every leaf LLR bit-exact, for saturating
-min-sum (POLAR_F_MINSUM_Q16) and the phi table (POLAR_F_PHI_Q16), at every
-size, pruned and unpruned, with leaf dumps, at N = 2^20 and 2^24, and the
-device's phi table equal to the oracle's."""
+min-sum (POLAR_F_MINSUM_Q16), the phi table (POLAR_F_PHI_Q16) and saturating
+min-sum on 8-bit integers (POLAR_F_MINSUM_Q8), at every size, pruned and
+unpruned, with leaf dumps, at N = 2^20 and 2^24, and the device's phi table
+equal to the oracle's."""
 import sys
 
 import numpy as np
@@ -16,7 +17,11 @@ from gpu_helpers import bsc_frames, biawgn_frames, decode
 
 pytestmark = pytest.mark.gpu
 
-KINDS = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI}  # library f_kind -> oracle kind
+KINDS = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI, 4: oracle.FIXED_MINSUM8}  # library f_kind -> oracle kind
+
+
+def _lim(fk):
+    return oracle.FIXED8_MAX if fk == 4 else oracle.FIXED_MAX
 
 
 def _say(msg):
@@ -35,24 +40,30 @@ def _need_gpu():
     lp.load()
 
 
-def _q(frames):
-    """Quantize the channel LLRs to units of 2^-4 (kept as float32 integers)."""
-    return [(oracle.quantize(llr).astype(np.float32), mask, fval) for llr, mask, fval in frames]
+def _q(frames, fk=2):
+    """Quantize the channel LLRs to units of 2^-4 (the 8-bit kind: 2^-2,
+    saturated to 127), kept as float32 integers."""
+    frac = 2 if fk == 4 else oracle.FIXED_FRAC
+    return [(oracle.quantize(llr, frac, _lim(fk)).astype(np.float32), mask, fval) for llr, mask, fval in frames]
 
 
-def _random_fixed_frames(log2n, g, count):
+def _random_fixed_frames(log2n, g, count, fk=2):
     n = 1 << log2n
+    lim = _lim(fk)
+    frac = 2 if fk == 4 else oracle.FIXED_FRAC
     out = []
     for k in range(count):
         kind = k % 4
         if kind == 0:
-            llr = np.where(g.random(n) < 0.1, -56, 56)                 # BSC 3% quantized
+            l0 = 14 if fk == 4 else 56
+            llr = np.where(g.random(n) < 0.1, -l0, l0)                 # BSC 3% quantized
         elif kind == 1:
-            llr = g.integers(-oracle.FIXED_MAX, oracle.FIXED_MAX + 1, n)  # saturating sums
+            llr = g.integers(-lim, lim + 1, n)                         # saturating sums
         elif kind == 2:
             llr = g.integers(-3, 4, n)                                 # zeros, tiny values
         else:
-            llr = oracle.quantize(2.0 * ((1 - 2 * g.integers(0, 2, n)) + 0.9 * g.standard_normal(n)) / 0.81)
+            llr = oracle.quantize(2.0 * ((1 - 2 * g.integers(0, 2, n)) + 0.9 * g.standard_normal(n)) / 0.81,
+                                  frac, lim)
         dens = [0.0, 1.0, 0.3, 0.5, 0.7][k % 5]
         mask = (g.random(n) < dens).astype(np.uint8)
         if k % 7 == 6:
@@ -82,11 +93,11 @@ def test_device_phi_table_equals_oracle_table():
     assert np.array_equal(t.cpu().numpy(), oracle.phi_table().astype(np.float32))
 
 
-@pytest.mark.parametrize("fk", [2, 3])
+@pytest.mark.parametrize("fk", [2, 3, 4])
 @pytest.mark.parametrize("log2n", list(range(1, 17)))
 def test_fixed_point_all_sizes_bit_exact(fk, log2n):
     g = np.random.default_rng(3000 + 100 * fk + log2n)
-    frames = _random_fixed_frames(log2n, g, 10 if log2n <= 13 else 5)
+    frames = _random_fixed_frames(log2n, g, 10 if log2n <= 13 else 5, fk)
     for prune in (True, False):
         _say(f"case: fixed f_kind={fk} log2n={log2n} prune={prune}")
         us, _ = decode(frames, f_kind=fk, prune=prune)
@@ -103,30 +114,31 @@ def test_fixed_point_all_sizes_bit_exact(fk, log2n):
         _check(frames, fk, us, what="plain")
 
 
-@pytest.mark.parametrize("fk", [2, 3])
+@pytest.mark.parametrize("fk", [2, 3, 4])
 def test_fixed_point_qkd_sizes(fk):
     """N = 2^20 BSC p = 0.03 rate 0.75 (16 frames) and N = 2^16 BIAWGN
-    sigma = 0.97 rate 0.45 (8 frames), channel LLRs quantized to 2^-4."""
-    frames = _q(bsc_frames(20, 0.03, 262144, range(2000, 2016)))
+    sigma = 0.97 rate 0.45 (8 frames), channel LLRs quantized to 2^-4
+    (8-bit kind: 2^-2, saturated to 127)."""
+    frames = _q(bsc_frames(20, 0.03, 262144, range(2000, 2016)), fk)
     _say(f"case: fixed f_kind={fk} N = 2^20 x16")
     us, _ = decode(frames, f_kind=fk)
     _check(frames, fk, us, what="2^20")
-    frames = _q(biawgn_frames(16, 0.97, (1 << 16) - int(0.45 * (1 << 16)), range(6500, 6508)))
+    frames = _q(biawgn_frames(16, 0.97, (1 << 16) - int(0.45 * (1 << 16)), range(6500, 6508)), fk)
     _say(f"case: fixed f_kind={fk} N = 2^16 BIAWGN x8 with leaf dump")
     us, leaves = decode(frames, f_kind=fk, prune=False, dump=True)
     _check(frames, fk, us, leaves, what="2^16 biawgn")
 
 
-@pytest.mark.parametrize("fk", [2, 3])
+@pytest.mark.parametrize("fk", [2, 3, 4])
 def test_fixed_point_max_size(fk):
-    frames = _q(bsc_frames(24, 0.03, (1 << 24) // 4, [7001]))
+    frames = _q(bsc_frames(24, 0.03, (1 << 24) // 4, [7001]), fk)
     _say(f"case: fixed f_kind={fk} N = 2^24")
     us, _ = decode(frames, f_kind=fk)
     _check(frames, fk, us, what="2^24")
 
 
 def test_fixed_point_mixed_with_float_kinds_in_one_batch():
-    """One batch holding all four check updates."""
+    """One batch holding all five check updates."""
     import torch
 
     from gpu_helpers import bits_host, frame_items
@@ -134,13 +146,13 @@ def test_fixed_point_mixed_with_float_kinds_in_one_batch():
     from paper_1204_5882_amd import polar as lp
 
     g = np.random.default_rng(3500)
-    frames = _random_fixed_frames(13, g, 8)
-    kinds = [k % 4 for k in range(8)]
+    kinds = [k % 5 for k in range(10)]
+    frames = [_random_fixed_frames(13, g, k + 1, fk if fk >= 2 else 2)[k] for k, fk in enumerate(kinds)]
     items = []
     for fr, fk in zip(frames, kinds):
         items += frame_items([fr], fk)
     ctx = lp.Ctx(0)
-    _say("case: four check updates in one batch")
+    _say("case: five check updates in one batch")
     ctx.decode(items)
     torch.cuda.synchronize()
     for k, (fr, fk, it) in enumerate(zip(frames, kinds, items)):

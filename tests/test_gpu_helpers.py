@@ -93,3 +93,18 @@ def test_one_frame_whole_gpu_and_mixed_sizes():
     us, _ = decode(frames, opts=_opts(1, 11))
     for k in range(len(frames)):
         assert np.array_equal(us[k], refs[k]), k
+
+
+def test_q8_with_helpers_bit_exact():
+    """8-bit kind, unpruned (the variant that takes helpers): the helpers
+    read the int8 level types from the mailbox."""
+    log2n = 21
+    frames = bsc_frames(log2n, 0.03, (1 << log2n) // 4, [9500, 9501, 9502])
+    qframes = [(synth.fixed_point(fr[0], frac=2, limit=127), fr[1], fr[2]) for fr in frames]
+    refs = [oracle.sc_decode_fixed(oracle.quantize(fr[0], 2, oracle.FIXED8_MAX), fr[1], fr[2],
+                                   oracle.FIXED_MINSUM8)[0] for fr in frames]
+    for helpers in (1, 0):
+        _say(f"case: 8-bit min-sum log2n=21 x3 unpruned helpers={helpers}")
+        us, _ = decode(qframes, f_kind=4, prune=False, opts=_opts(helpers))
+        for k in range(3):
+            assert np.array_equal(us[k], refs[k]), (helpers, k)

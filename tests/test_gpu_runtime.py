@@ -527,3 +527,46 @@ def test_serving_waits_for_inputs_on_the_input_stream():
         assert done[k][0] == lp.POLAR_OK
         assert np.array_equal(bits_host(it["u_hat"], 1 << 16), refs[k]), k
     ctx.close()
+
+
+def test_serving_every_check_update_kind():
+    """Requests of all five check updates (FP32 min-sum and box-plus, 16-bit
+    saturating min-sum and phi table, 8-bit saturating min-sum) through one
+    server: each equals its solo decode, the fixed-point ones the oracle."""
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    frames = _mixed_frames(10, 12, 16, seed=93)
+    kinds = [k % 5 for k in range(10)]
+    inputs = []
+    for fr, fk in zip(frames, kinds):
+        llr = fr[0]
+        if fk in (2, 3):
+            llr = oracle.quantize(llr).astype(np.float32)
+        elif fk == 4:
+            llr = oracle.quantize(llr, 2, oracle.FIXED8_MAX).astype(np.float32)
+        inputs.append((llr, fr[1], fr[2]))
+    items = []
+    for fr, fk in zip(inputs, kinds):
+        items += frame_items([fr], fk)
+    ctx = lp.Ctx(0)
+    arena = torch.empty(128 << 20, dtype=torch.uint8, device="cuda")
+    srv = lp.Server(ctx, arena, max_slots=4, poll_us=0)
+    done = {}
+    _say("case: serving ten requests of five check-update kinds")
+    for k, it in enumerate(items):
+        srv.submit(it, 300 + k)
+    _drain(srv, done)
+    srv.close()
+    torch.cuda.synchronize()
+    fixed = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI, 4: oracle.FIXED_MINSUM8}
+    for k, (it, fr, fk) in enumerate(zip(items, inputs, kinds)):
+        assert done[300 + k][0] == lp.POLAR_OK
+        u = bits_host(it["u_hat"], it["llr"].numel())
+        solo, _ = decode([fr], f_kind=fk)
+        assert np.array_equal(u, solo[0]), k
+        if fk in fixed:
+            assert np.array_equal(u, oracle.sc_decode_fixed(fr[0].astype(np.int32), fr[1], fr[2], fixed[fk])[0]), k
+        elif fk == 0:
+            assert np.array_equal(u, oracle.sc_decode(*fr)[0]), k
+    ctx.close()
