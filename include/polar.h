@@ -76,7 +76,7 @@ extern "C" {
 
 /* List decoding: paths per frame, and the largest N x paths (state on chip). */
 #define POLAR_SCL_MAX_LIST 16
-#define POLAR_SCL_MAX_NL 16384
+#define POLAR_SCL_MAX_NL 32768  /* every path's state in the 160 KiB of LDS */
 
 /* Degrading construction: outputs kept per channel, and outputs of the
    channel it starts from. */

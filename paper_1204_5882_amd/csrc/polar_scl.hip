@@ -294,6 +294,7 @@ extern "C" int polar_scl_decode_batch(polar_ctx* c, const polar_frame* frames, i
     if (rc) return rc;
     // one wavefront per frame; LDS sized for the largest frame of the batch
     const size_t smem = scl_lds_bytes(max_log, list_size);
+    if (smem > 160 * 1024) return fail(POLAR_E_INVAL, "list decoder needs %zu bytes of LDS", smem);
     if (smem > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_scl_decode, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)smem);

@@ -48,7 +48,7 @@ POLAR_STATIC_SCRATCH_BYTES = 256 << 20
 POLAR_STATIC_MAX_FRAMES = 16384
 POLAR_CONSTRUCT_MAX_MU = 64
 POLAR_SCL_MAX_LIST = 16
-POLAR_SCL_MAX_NL = 16384
+POLAR_SCL_MAX_NL = 32768
 POLAR_CONSTRUCT_MAX_OUTPUTS = 65536
 
 # every symbol declared in include/polar.h

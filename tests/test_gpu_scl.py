@@ -1,6 +1,6 @@
 """GPU parity of SC list decoding (polar_scl_decode_batch) with the oracle
 (oracle.scl_decode): decisions and the chosen path's metric, exactly, for
-list sizes 1..16 and N up to the on-chip limit N x L <= 16384, on random
+list sizes 1..16 and N up to the on-chip limit N x L <= 32768, on random
 masks (including ties: LLRs on a coarse grid, exact zeros) and on
 Bhattacharyya-built codes; a batch mixing sizes; argument errors."""
 import sys
@@ -67,7 +67,7 @@ def _gpu_scl(frames, list_size):
 
 
 CASES = [(1, 1), (1, 4), (2, 2), (3, 8), (5, 16), (6, 4), (8, 8), (10, 1), (10, 8), (10, 16), (11, 8), (12, 4),
-         (13, 2), (14, 1)]
+         (13, 2), (14, 1), (11, 16), (12, 8), (13, 4), (14, 2), (15, 1)]
 
 
 @pytest.mark.parametrize("log2n,list_size", CASES)
@@ -118,8 +118,8 @@ def test_argument_errors():
     for bad_l in (0, 17):
         with pytest.raises(lp.PolarError):
             ctx.scl_decode(frame_items(fr, 0), bad_l)
-    with pytest.raises(lp.PolarError):  # N x L = 2^12 x 8 > 16384
-        ctx.scl_decode(frame_items(fr, 0), 8)
+    with pytest.raises(lp.PolarError):  # N x L = 2^12 x 16 > 32768
+        ctx.scl_decode(frame_items(fr, 0), 16)
     with pytest.raises(lp.PolarError):  # box-plus
         ctx.scl_decode(frame_items(fr, 1), 2)
     torch.cuda.synchronize()
