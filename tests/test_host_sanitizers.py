@@ -6,7 +6,7 @@ flag goes to the host pass); the device code of the construction's file is
 compiled as usual and never launched.  Any out-of-bounds access, leak,
 overflow or other undefined behaviour aborts the driver.  (The planner once
 sized a stack array for four check-update kinds; with a fifth kind the
-driver's plans index past it, which this build reports.)"""
+driver's plans index past it, which the sanitized driver reports.)"""
 import os
 import shutil
 import subprocess
