@@ -349,9 +349,11 @@ int polar_tune_load(polar_ctx* ctx, const char* path);
  * side).  Requests (one frame each, caller-owned device buffers that must
  * stay valid until the request completes) are queued, admitted against a
  * caller-provided device arena and decoded in batches by the batch decoder on
- * up to four internal streams at once: a new batch starts on an idle stream
+ * up to three internal streams at once: a new batch starts on an idle stream
  * with the requests that have arrived, in arrival order, as many as fit the
- * free arena (and at most max_slots), while earlier batches still run.  Each
+ * free arena (and at most max_slots), while earlier batches still run.  One
+ * of the streams takes only requests of at most 2^17 bits, so that small
+ * requests never wait for a stream behind batches of large frames.  Each
  * request is charged its own footprint in the arena: a 64-byte descriptor
  * plus, above 2^12 leaves, a scratch slot of about 4N + N/8 bytes for its own
  * N (256 bytes of counters per batch).  A request too large for the whole

@@ -4,7 +4,12 @@
 // earlier batches still run (continuous batching).
 //
 // Admission: a batch takes requests from the head of the queue in arrival
-// order while its workspace fits a free range of the arena.  Each request is
+// order while its workspace fits a free range of the arena.  One stream is
+// kept for small requests (at most 2^kSmallLog2N bits, about a millisecond of
+// decoding): a batch holding a large frame keeps its stream for tens of
+// milliseconds while using a few compute units, and would otherwise make the
+// small requests behind it wait for a stream.  The small stream takes the
+// small requests in arrival order, the others take every request.  Each request is
 // charged its own footprint: a descriptor and a scratch slot sized for its
 // own N (per-frame slots), so admission follows the frames' sizes, not the
 // largest frame of the batch.  A request that cannot fit even an empty arena
@@ -32,7 +37,13 @@ using namespace polar_host;
 
 namespace {
 
-constexpr int kStreams = 4;
+// Streams of the server.  HIP gives a process four hardware queues by
+// default, and the caller's own stream holds one: a fourth server stream
+// would share a queue with another stream, and a small request's kernel
+// would then wait behind a large batch's (measured: 2^16 requests at 5-13 ms
+// p50 with four streams, 0.6-1.2 ms with three).
+constexpr int kStreams = 3;
+constexpr int kSmallLog2N = 17;  // stream 0 takes only requests of at most 2^17 bits
 constexpr size_t kQueueCap = 1 << 16;
 
 double now_s() {
@@ -172,7 +183,8 @@ int reap(polar_server* s) {
 // Start batches on idle streams while requests wait and fit.
 int launch(polar_server* s) {
     polar_ctx* c = s->ctx;
-    for (auto& b : s->batch) {
+    for (int si = 0; si < kStreams; ++si) {
+        Batch& b = s->batch[si];
         if (b.active || s->queue.empty()) continue;
         // requests that cannot fit even an empty arena
         while (!s->queue.empty()) {
@@ -181,6 +193,7 @@ int launch(polar_server* s) {
             s->queue.pop_front();
         }
         if (s->queue.empty()) break;
+        const bool small_only = si == 0;
         // the largest free range bounds the batch
         size_t free_max = 0;
         {
@@ -193,24 +206,44 @@ int launch(polar_server* s) {
             free_max = lo;
         }
         std::vector<polar_frame> fr;
+        std::vector<size_t> taken;  // queue positions, increasing
         BatchSize bs;
         size_t need = 0, off = 0;
-        int take = 0;
         const int limit = std::min<int>(s->max_batch, (int)s->free_flags.size());
-        for (const auto& r : s->queue) {
-            if (take >= limit) break;
+        for (size_t qi = 0; qi < s->queue.size() && (int)taken.size() < limit; ++qi) {
+            const Req& r = s->queue[qi];
+            if (small_only && r.f.log2n > kSmallLog2N) continue;
             const size_t nb = bs.total_with(c, r.f);
             if (nb > free_max) break;
             bs.add(r.f);
             fr.push_back(r.f);
+            taken.push_back(qi);
             need = nb;
-            ++take;
         }
-        if (take == 0) break;  // the head waits for memory
+        if (taken.empty()) {
+            if (small_only) continue;  // no small request waits
+            break;                     // the head waits for memory
+        }
         if (!arena_find(s, need, &off)) break;
+        const int take = (int)taken.size();
         Plan p;
         make_plan(c, fr.data(), take, false, p, nullptr, true);
-        std::vector<Req> reqs(s->queue.begin(), s->queue.begin() + take);
+        std::vector<Req> reqs;
+        reqs.reserve(taken.size());
+        for (size_t qi : taken) reqs.push_back(s->queue[qi]);
+        // the requests left in the queue, in arrival order
+        const auto drop_taken = [&]() {
+            std::deque<Req> rest;
+            size_t t = 0;
+            for (size_t qi = 0; qi < s->queue.size(); ++qi) {
+                if (t < taken.size() && taken[t] == qi) {
+                    ++t;
+                    continue;
+                }
+                rest.push_back(s->queue[qi]);
+            }
+            s->queue.swap(rest);
+        };
         for (size_t k = 0; k < p.descs.size(); ++k) {
             Req& r = reqs[(size_t)p.order[k]];
             r.flag = s->free_flags.back();
@@ -222,7 +255,7 @@ int launch(polar_server* s) {
         }
         // the batch starts after the work already enqueued on the input stream
         TraceRange tr("polar_serve batch");
-        log_line("serve: batch of %zu requests, %zu workspace bytes", p.descs.size(), need);
+        log_line("serve: batch of %zu requests on stream %d, %zu workspace bytes", p.descs.size(), si, need);
         hipError_t e = hipEventRecord(b.inputs, s->input_stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.inputs, 0);
         int rc = e == hipSuccess ? run_plan(c, p, s->arena + off, need, b.stream, b.stager, false, s->flags)
@@ -232,7 +265,7 @@ int launch(polar_server* s) {
                 if (r.flag != 0xffffffffu) s->free_flags.push_back(r.flag);
                 complete(s, r.id, rc, r.t_submit);
             }
-            s->queue.erase(s->queue.begin(), s->queue.begin() + take);
+            drop_taken();
             return rc;
         }
         e = hipEventRecord(b.done, b.stream);
@@ -240,7 +273,7 @@ int launch(polar_server* s) {
         b.off = off;
         b.bytes = need;
         b.reqs = std::move(reqs);
-        s->queue.erase(s->queue.begin(), s->queue.begin() + take);
+        drop_taken();
         if (e != hipSuccess) return hip_fail(e, "serving event");
     }
     return ok();
