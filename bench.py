@@ -564,7 +564,7 @@ def main(argv=None):
     ap.add_argument("--cutover", type=int, default=0, help="register-resident subtree log2 (0 = library default)")
     ap.add_argument("--fwg", type=int, default=0,
                     help="frames per workgroup for frames of at most 2^cutover leaves (0 = library default)")
-    ap.add_argument("--graph", type=int, default=0, help="replay the batch through a HIP graph")
+    ap.add_argument("--graph", type=int, default=1, help="replay the batch through a HIP graph (0: launch it directly)")
     ap.add_argument("--helpers", type=int, default=1,
                     help="spare resident workgroups share the large sweeps of frames (when frames < workgroups)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
