@@ -570,3 +570,45 @@ def test_serving_every_check_update_kind():
         elif fk == 0:
             assert np.array_equal(u, oracle.sc_decode(*fr)[0]), k
     ctx.close()
+
+
+def test_serving_small_request_passes_large_batches():
+    """Three 2^22 requests fill the server's general streams; a 2^16 request
+    submitted after them runs on the stream kept for small requests and
+    completes while they still decode.  Every result equals its solo decode."""
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    big = bsc_frames(22, 0.03, 1 << 20, [9800, 9801, 9802])
+    small = bsc_frames(16, 0.03, 1 << 14, [9803])
+    frames = big + small
+    ctx = lp.Ctx(0)
+    arena = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    srv = lp.Server(ctx, arena, poll_us=0)
+    items = frame_items(frames)
+    torch.cuda.synchronize()
+    _say("case: one 2^16 request behind three 2^22 requests")
+    order = []
+    for k, it in enumerate(items[:3]):
+        srv.submit(it, 500 + k)
+        for rid, st, _ in srv.poll():  # start each large request in its own batch
+            order.append(rid)
+    srv.submit(items[3], 503)
+    done = {}
+    t0 = time.time()
+    while srv.pending() != (0, 0, 0):
+        for rid, st, lat in srv.poll():
+            done[rid] = (st, lat)
+            order.append(rid)
+        assert time.time() - t0 < 60.0, "serving stalled"
+        time.sleep(0.0002)
+    srv.close()
+    torch.cuda.synchronize()
+    assert sorted(order) == [500, 501, 502, 503]
+    assert order[0] == 503, order  # the small request finished first
+    assert done[503][1] < min(done[k][1] for k in (500, 501, 502))
+    refs = oracle_many(frames)
+    for k, it in enumerate(items):
+        assert done[500 + k][0] == lp.POLAR_OK
+        assert np.array_equal(bits_host(it["u_hat"], it["llr"].numel()), refs[k]), k
+    ctx.close()
