@@ -486,6 +486,63 @@ def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1,
                 points=out, note="the paper's frozen sets come from density evolution [MT09]")
 
 
+def workloads_leg(lp, torch, dev, names=("n12-bsc-x64", "n24-biawgn-boxplus-x16", "mixed-n16-22-x512"),
+                  steps=3, warmup=1, check_frames=4):
+    """The other configured workloads, each timed like the headline (graph
+    replay, pruning, helpers; the mixed batch autotuned first), with the
+    roofline fraction of its algorithmic bytes and an oracle check of the
+    timed output on a sample: min-sum bit for bit on the smallest
+    check_frames frames, box-plus on one frame by the teacher-forced FP64
+    oracle (frozen positions equal, decisions differing only where
+    |L_ref| < 1e-6)."""
+    import oracle
+
+    out = {}
+    for name in names:
+        cfg = CONFIGS[name]
+        print(f"[bench] workload {name}", file=sys.stderr, flush=True)
+        items, host = make_inputs(name, lp, torch, dev)
+        n = len(items)
+        bits = sum(1 << it["log2n"] for it in items)
+        ctx = lp.Ctx(0)
+        ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
+        frames = lp.make_frames(items)
+        tuned = ctx.autotune(items, reps=3) if name.startswith("mixed") else None
+        ctx.ensure_workspace(frames, n)
+        torch.cuda.synchronize()
+        wall, per = time_batched(ctx, frames, n, steps, warmup, torch)
+        ms = wall / steps * 1e3
+        ev = float(np.mean(per))
+        alg = sum((1 << it["log2n"]) * bytes_per_bit(it["log2n"]) for it in items)
+        rec = dict(desc=cfg["desc"], frames=n, bits_per_step=bits, ms_per_step=round(ms, 3),
+                   Mbit_s=round(bits / (ms / 1e3) / 1e6, 1), kernel_ms_mean=round(ev, 3),
+                   roofline_frac=round(alg / (ev / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                   launch=ctx.query_launch(cfg["fkind"], max(it["log2n"] for it in items), n), tuned=tuned)
+        # oracle check of the timed output
+        if cfg["fkind"] == 1:
+            k = 0
+            got = synth.unpack_bits(items[k]["u_hat"].cpu().numpy().view(np.uint32), items[k]["llr"].numel())
+            llr, mask, fval = host[k]
+            u_or, l_ref, _ = oracle.sc_decode(llr, mask, fval, boxplus=True, teacher=got, want_leaf=True)
+            fz = mask == 1
+            dis = (u_or != got) & ~fz
+            ok = bool(np.array_equal(got[fz], fval[fz])) and bool(np.all(np.abs(l_ref[dis]) < 1e-6))
+            rec["oracle_check"] = dict(frames=1, rule="teacher-forced FP64 oracle, |L_ref| < 1e-6 at differing "
+                                       "decisions", tolerated_differences=int(dis.sum()), agrees=ok)
+        else:
+            order = sorted(range(n), key=lambda i: items[i]["log2n"])[:check_frames]
+            ok = True
+            for k in order:
+                got = synth.unpack_bits(items[k]["u_hat"].cpu().numpy().view(np.uint32), items[k]["llr"].numel())
+                ok &= bool(np.array_equal(got, oracle.sc_decode(*host[k])[0]))
+            rec["oracle_check"] = dict(frames=len(order), rule="bit-exact", agrees=ok)
+        out[name] = rec
+        ctx.close()
+        del ctx, items, host, frames
+        torch.cuda.empty_cache()
+    return out
+
+
 def scl_leg(lp, torch, dev, log2n=10, p=0.05, k_info=563, n_frames=4096, lists=(1, 2, 4, 8, 16), seed=4242):
     """SC list decoding on the device: frame error rate and decoding rate per
     list size on synthetic BSC frames (the harness's generator), one code
@@ -575,6 +632,8 @@ def main(argv=None):
                     help="autotune the launch on the workload first (default: on for the mixed workload)")
     ap.add_argument("--no-fer", action="store_true", help="skip the FER / efficiency leg")
     ap.add_argument("--no-scl", action="store_true", help="skip the SC list decoding leg")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other configured workloads (timed and oracle-checked after the headline)")
     ap.add_argument("--per-frame-frames", type=int, default=8,
                     help="frames timed with the per-frame whole-GPU decoder (one batched call per frame)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -712,6 +771,8 @@ def main(argv=None):
                                 note="the batched decoder given one frame per call, serial on one stream")
         out["speedup_vs_per_frame"] = round(value / (pbits / pw / 1e6), 1)
 
+    if not args.no_workloads and args.config == "n20-bsc-x256":
+        out["workloads"] = workloads_leg(lp, torch, dev)
     if not args.no_scl:
         print("[bench] SC list decoding leg", flush=True)
         out["scl"] = scl_leg(lp, torch, dev)
