@@ -486,10 +486,17 @@ def fer_leg(lp, torch, dev, p=0.02, sizes=(16, 20, 24), frames=None, target=0.1,
                 points=out, note="the paper's frozen sets come from density evolution [MT09]")
 
 
+def tuned_by_default(name):
+    """Workloads whose launch the autotuner picks before timing: the mixed
+    batch, and the 2^12 frames (fewer than the compute units: a lower cutover
+    puts each on a whole workgroup).  The headline keeps the default launch."""
+    return name.startswith("mixed") or name == "n12-bsc-x64"
+
+
 def workloads_leg(lp, torch, dev, names=("n12-bsc-x64", "n24-biawgn-boxplus-x16", "mixed-n16-22-x512"),
                   steps=3, warmup=1, check_frames=4):
     """The other configured workloads, each timed like the headline (graph
-    replay, pruning, helpers; the mixed batch autotuned first), with the
+    replay, pruning, helpers; autotuned first where tuned_by_default), with the
     roofline fraction of its algorithmic bytes and an oracle check of the
     timed output on a sample: min-sum bit for bit on the smallest
     check_frames frames, box-plus on one frame by the teacher-forced FP64
@@ -507,7 +514,7 @@ def workloads_leg(lp, torch, dev, names=("n12-bsc-x64", "n24-biawgn-boxplus-x16"
         ctx = lp.Ctx(0)
         ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
         frames = lp.make_frames(items)
-        tuned = ctx.autotune(items, reps=3) if name.startswith("mixed") else None
+        tuned = ctx.autotune(items, reps=3) if tuned_by_default(name) else None
         ctx.ensure_workspace(frames, n)
         torch.cuda.synchronize()
         wall, per = time_batched(ctx, frames, n, steps, warmup, torch)
@@ -629,7 +636,7 @@ def main(argv=None):
     ap.add_argument("--serve-arena-gb", type=float, default=200.0,
                     help="serving arena (device memory admission budget), GB")
     ap.add_argument("--tune", type=int, default=-1,
-                    help="autotune the launch on the workload first (default: on for the mixed workload)")
+                    help="autotune the launch on the workload first (default: on for the mixed and 2^12 workloads)")
     ap.add_argument("--no-fer", action="store_true", help="skip the FER / efficiency leg")
     ap.add_argument("--no-scl", action="store_true", help="skip the SC list decoding leg")
     ap.add_argument("--no-workloads", action="store_true",
@@ -679,7 +686,7 @@ def main(argv=None):
     if args.graph:
         ctx.set_option(lp.POLAR_OPT_GRAPH, 1)
     frames = lp.make_frames(items)
-    tune = args.tune if args.tune >= 0 else int(args.config.startswith("mixed"))
+    tune = args.tune if args.tune >= 0 else int(tuned_by_default(args.config))
     tuned = None
     if tune:
         print("[bench] autotuning the launch on this workload", file=sys.stderr, flush=True)
