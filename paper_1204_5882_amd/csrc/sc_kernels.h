@@ -321,10 +321,16 @@ __device__ __forceinline__ float gupd(float a, float b, uint32_t sgn) {
 // alpha = (0, -1) gives x-hat = (1, 1).)
 //   min-sum: an LLR inside the node is zero only if the node has an input
 //            that is zero, so "no input LLR is zero" suffices (floor 0);
-//   box-plus: f can also underflow to zero.  For |a|, |b| >= 1 the log form
-//            gives |f| >= min(|a|,|b|) - ln 2, and |g| >= min(|a|,|b|) in a
-//            rate-1 node, so inputs above 1 + L ln 2 keep every LLR of a
-//            node of size 2^L at or above 1.
+//   box-plus: f of small inputs is tiny (f(x, x) ~ x^2 / 2) and can round
+//            to zero.  f grows with both magnitudes and g adds them in a
+//            rate-1 node, so the smallest LLR of a node of size 2^L whose
+//            inputs are all at least F is at least f applied L times along
+//            the left spine, x -> f(x, x) from F.  The floor F_L is the
+//            least F (rounded up) for which that exceeds 1e-5 in exact
+//            arithmetic: then every exact LLR of the node is at least 1e-5
+//            with the sign the hard decisions assume, so SC decides them
+//            (in exact arithmetic, in the FP64 reference, and in FP32, whose
+//            deviation stays far inside the margin).
 // Below the floor the decoder descends into the node like any other, which
 // is SC by construction; its children are checked again.
 //   saturating min-sum (FK = 2, 4): as min-sum (a saturated sum of two terms
@@ -336,10 +342,13 @@ __device__ __forceinline__ float gupd(float a, float b, uint32_t sgn) {
 //            min-sum there and keeps the bound, as g does, so inputs of 67
 //            and above (floor 66, any L) make the hard decisions SC.  67 is
 //            the least bound closed under f: T[T[66] + T[66]] = T[2] = 44.
+constexpr float BOXPLUS_FLOOR[13] = {0.0f,  0.01f, 0.10f, 0.45f, 1.02f, 1.68f, 2.37f,
+                                     3.06f, 3.75f, 4.44f, 5.13f, 5.83f, 6.52f};
+
 template <int FK>
 __host__ __device__ constexpr float rate1_floor(int L) {
     return minsum_kind<FK>()    ? 0.0f
-           : FK == 1            ? 1.0f + 0.69314718f * (float)L + 0.01f
+           : FK == 1            ? BOXPLUS_FLOOR[L]
                                 : 66.0f;
 }
 

@@ -332,3 +332,67 @@ def test_phi_rate1_below_floor_is_not_hard_decision():
         u, _ = oracle.sc_decode_fixed(llr, np.zeros(64, np.uint8), np.zeros(64, np.uint8), oracle.FIXED_PHI)
         differs += not np.array_equal(oracle.encode(6, u), (llr < 0).astype(np.uint8))
     assert differs > 0
+
+
+# ---------------------------------------------------------------------------
+# Rate-1 floor of exact box-plus: with every input magnitude of a node of
+# 2^L leaves at least F_L, every exact LLR inside the node is at least 1e-5
+# (the smallest lies on the left spine, x -> f(x, x) applied L times), so SC
+# takes the hard decisions.  The kernel's table holds F_L rounded up.
+# ---------------------------------------------------------------------------
+def _kernel_boxplus_floor():
+    src = open(SRC).read()
+    body = src[src.index("constexpr float BOXPLUS_FLOOR[13]"):]
+    body = body[body.index("{") + 1: body.index("}")]
+    return [float(x.strip().rstrip("f")) for x in body.split(",")]
+
+
+def _spine_threshold(L, target="1e-5"):
+    import mpmath as mp
+
+    mp.mp.dps = 50
+    f = lambda x: 2 * mp.atanh(mp.tanh(x / 2) ** 2)  # noqa: E731
+    lo, hi = mp.mpf(0), mp.mpf(20)
+    for _ in range(120):
+        mid = (lo + hi) / 2
+        x = mid
+        for _ in range(L):
+            x = f(x)
+        if x >= mp.mpf(target):
+            hi = mid
+        else:
+            lo = mid
+    return float(hi)
+
+
+def test_boxplus_floor_table_is_tight_and_safe():
+    table = _kernel_boxplus_floor()
+    assert len(table) == 13 and table[0] == 0.0
+    for L in range(1, 13):
+        t = _spine_threshold(L)
+        assert t <= table[L] < t + 0.02, (L, t, table[L])
+    assert all(b > a for a, b in zip(table, table[1:]))
+
+
+@pytest.mark.parametrize("L", [1, 3, 6, 9, 12])
+def test_boxplus_rate1_above_floor_is_hard_decision(L):
+    table = _kernel_boxplus_floor()
+    g = np.random.default_rng(400 + L)
+    m = 1 << L
+    zero = np.zeros(m, np.uint8)
+    for trial in range(20 if L < 12 else 4):
+        mag = table[L] + (g.exponential(0.5, m) if trial % 2 else np.where(g.random(m) < 0.7, 0.0, g.random(m)))
+        llr = (mag * (1 - 2 * g.integers(0, 2, m))).astype(np.float32)
+        llr = np.where(np.abs(llr) < table[L], np.copysign(np.float32(table[L]), llr), llr).astype(np.float32)
+        u, leaf, beta = oracle.sc_decode(llr, zero, zero, boxplus=True, want_leaf=True, want_beta=True)
+        assert np.array_equal(beta, (llr < 0).astype(np.uint8))
+        assert np.abs(leaf).min() >= 1e-5 * 0.99
+
+
+def test_boxplus_below_floor_can_reach_tiny_llrs():
+    # inputs at half the floor drive the left spine far below 1e-5
+    table = _kernel_boxplus_floor()
+    m = 1 << 6
+    llr = np.full(m, table[6] / 2, np.float32)
+    _, leaf, _ = oracle.sc_decode(llr, np.zeros(m, np.uint8), np.zeros(m, np.uint8), boxplus=True, want_leaf=True)
+    assert np.abs(leaf).min() < 1e-5
