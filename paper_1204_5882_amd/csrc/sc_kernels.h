@@ -224,16 +224,39 @@ __device__ __forceinline__ float log1p_pos(float z) {
     const float r = hw_log(u) * (z * hw_rcp(d));  // d = 0 or d >= 2^-24: normal
     return d == 0.0f ? z : r;
 }
+// The two forms on magnitudes A, B.  tanh form: argument clamped (tanh(x/2)
+// is 1 in FP32 beyond x = 40).
+__device__ __forceinline__ float boxplus_tanh_form(float A, float B) {
+    const float ea = expm1_pos(fminf(A, 40.0f));
+    const float eb = expm1_pos(fminf(B, 40.0f));
+    return log1p_pos(ea * eb * hw_rcp(ea + eb + 2.0f));
+}
+__device__ __forceinline__ float boxplus_log_form(float A, float B) {
+    return fminf(A, B) + log1p_pos(hw_exp(-(A + B))) - log1p_pos(hw_exp(-fabsf(A - B)));
+}
 __device__ __forceinline__ float f_boxplus(float a, float b) {
     const float A = fabsf(a), B = fabsf(b);
     const float m = fminf(A, B);
-    // tanh form (argument clamped: tanh(x/2) is 1 in FP32 beyond x = 40)
-    const float ea = expm1_pos(fminf(A, 40.0f));
-    const float eb = expm1_pos(fminf(B, 40.0f));
-    const float r_small = log1p_pos(ea * eb * hw_rcp(ea + eb + 2.0f));
-    // log form
-    const float r_large = m + log1p_pos(hw_exp(-(A + B))) - log1p_pos(hw_exp(-fabsf(A - B)));
+    const float r_small = boxplus_tanh_form(A, B);
+    const float r_large = boxplus_log_form(A, B);
     const float r = (m <= 1.0f) ? r_small : r_large;
+    const uint32_t s = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
+    return __uint_as_float(__float_as_uint(r) | s);
+}
+// The same update on the lanes of one node of the block decoder (lanes: the
+// lanes whose result is used; the wavefront is fully active there).  The
+// tanh form is evaluated only when one of those lanes selects it, so a node
+// whose smaller inputs all exceed 1 pays for the log form alone.  (Skipping
+// the log form too where every lane selects the tanh form measured slower.)
+// Results on those lanes are f_boxplus's.
+__device__ __forceinline__ float f_boxplus_on(float a, float b, uint64_t lanes) {
+    const float A = fabsf(a), B = fabsf(b);
+    const float m = fminf(A, B);
+    float r = boxplus_log_form(A, B);
+    if ((ballot(m <= 1.0f) & lanes) != 0) {
+        const float r_small = boxplus_tanh_form(A, B);
+        r = (m <= 1.0f) ? r_small : r;
+    }
     const uint32_t s = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
     return __uint_as_float(__float_as_uint(r) | s);
 }
@@ -299,6 +322,13 @@ __device__ __forceinline__ float fupd(float a, float b) {
     if constexpr (minsum_kind<FK>()) return f_minsum(a, b);
     else if constexpr (FK == 1) return f_boxplus(a, b);
     else return f_phi(a, b);
+}
+
+// f whose result is used on the given lanes only (the block decoder's nodes).
+template <int FK>
+__device__ __forceinline__ float fupd_on(float a, float b, uint64_t lanes) {
+    if constexpr (FK == 1) return f_boxplus_on(a, b, lanes);
+    else return fupd<FK>(a, b);
 }
 
 // The variable update's sum, saturated for the fixed-point kinds.
@@ -520,7 +550,7 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
         if (((low >> O) & ALL) == 0) {
             bn = dec_sign(a);
         } else {
-            const float c = fupd<FK>(a, lane_downf<H>(a));
+            const float c = fupd_on<FK>(a, lane_downf<H>(a), ones64(H) << O);
             const uint32_t bl = sl_node<H, 0, FK, DUMP>(c, O, B);
             const float d = gsat<FK>(a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bl)));
             const uint32_t br = sl_node<H, 0, FK, DUMP>(d, O + H, B);
@@ -539,7 +569,7 @@ __device__ __forceinline__ uint32_t sl_node(float a, int O, Blk& B) {
     } else {
         constexpr int H = M / 2;
         constexpr uint64_t LO = ones64(H);
-        const float c = fupd<FK>(a, lane_downf<H>(a));
+        const float c = fupd_on<FK>(a, lane_downf<H>(a), ones64(H) << O);
         const uint32_t bl = sl_node<H, (P & LO), FK, DUMP>(c, O, B);
         const float d = gsat<FK>(a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ bl)));
         const uint32_t br = sl_node<H, (P >> H), FK, DUMP>(d, O + H, B);
@@ -714,7 +744,7 @@ __device__ __forceinline__ void blk_generic(float a, int O, Blk& B) {
             for (int side = 0; side < 2; ++side) {
                 float c;
                 if (side == 0) {
-                    c = fupd<FK>(a, lane_downf<H>(a));  // left child, lanes [O, O + H)
+                    c = fupd_on<FK>(a, lane_downf<H>(a), ones64(H) << O);  // left child, lanes [O, O + H)
                 } else {
                     c = gsat<FK>(a + __uint_as_float(lane_up<H>(__float_as_uint(a) ^ B.beta)));  // right child
                 }
