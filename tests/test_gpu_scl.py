@@ -2,7 +2,8 @@
 (oracle.scl_decode): decisions and the chosen path's metric, exactly, for
 list sizes 1..16 and N up to the on-chip limit N x L <= 32768, on random
 masks (including ties: LLRs on a coarse grid, exact zeros) and on
-Bhattacharyya-built codes; a batch mixing sizes; argument errors."""
+Bhattacharyya-built codes; a batch mixing sizes; a seeded random sweep;
+argument errors."""
 import sys
 
 import numpy as np
@@ -123,4 +124,47 @@ def test_argument_errors():
     with pytest.raises(lp.PolarError):  # box-plus
         ctx.scl_decode(frame_items(fr, 1), 2)
     torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_random_sweep_matches_oracle():
+    """400 seeded trials: list size 1..16, a batch of 1..5 frames with
+    N x L <= 32768, masks of random density, Bhattacharyya-built or uniform,
+    LLRs Gaussian, on a coarse grid with zeros, or BSC."""
+    import torch
+
+    from paper_1204_5882_amd import polar as lp
+
+    ctx = lp.Ctx(0)
+    for seed in range(400):
+        g = np.random.default_rng(10_000 + seed)
+        lsz = int(g.integers(1, 17))
+        maxlog = min(15, (32768 // lsz).bit_length() - 1)
+        logs = [int(g.integers(1, maxlog + 1)) for _ in range(int(g.integers(1, 6)))]
+        frames = []
+        for log2n in logs:
+            n = 1 << log2n
+            mk = int(g.integers(0, 3))
+            if mk == 0:
+                mask = (g.random(n) < g.uniform(0, 1)).astype(np.uint8)
+            elif mk == 1:
+                mask = np.asarray(oracle.frozen_set(log2n, float(g.uniform(0.05, 0.6)), int(g.integers(0, n + 1)))[0],
+                                  np.uint8)
+            else:
+                mask = np.full(n, int(g.integers(0, 2)), np.uint8)
+            fval = (g.integers(0, 2, n) & mask).astype(np.uint8)
+            lk = int(g.integers(0, 3))
+            llr = (g.standard_normal(n) * 2 if lk == 0 else g.integers(-8, 9, n) * 0.25 if lk == 1
+                   else np.where(g.random(n) < 0.05, -3.476, 3.476))
+            frames.append((np.asarray(llr, np.float32), mask, fval))
+        _say(f"case: scl sweep seed {seed} L={lsz} log2n={logs}")
+        items = frame_items(frames, 0)
+        pm = torch.full((len(frames),), -1.0, dtype=torch.float32, device="cuda")
+        ctx.scl_decode(items, lsz, path_metric=pm)
+        torch.cuda.synchronize()
+        pms = pm.cpu().numpy()
+        for k, fr in enumerate(frames):
+            u = bits_host(items[k]["u_hat"], fr[0].size)
+            ref_u, ref_pm = oracle.scl_decode(*fr, lsz)
+            assert np.array_equal(u, ref_u) and pms[k] == ref_pm, (seed, k)
     ctx.close()
