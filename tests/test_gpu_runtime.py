@@ -612,3 +612,59 @@ def test_serving_small_request_passes_large_batches():
         assert done[500 + k][0] == lp.POLAR_OK
         assert np.array_equal(bits_host(it["u_hat"], it["llr"].numel()), refs[k]), k
     ctx.close()
+
+
+def test_serving_random_sweep_matches_oracle():
+    """60 seeded trials: 1..39 requests of FP32 min-sum and the fixed-point
+    kinds, N = 2^1 .. 2^18, submitted with random interleaved polls into
+    arenas of 1 MiB to 256 MiB with several batch limits.  Every request is
+    reported once; those that fit the arena equal the oracle, the others
+    (2^18 in 1 MiB) complete with POLAR_E_NOMEM."""
+    import torch
+    from paper_1204_5882_amd import polar as lp
+
+    kinds = {2: oracle.FIXED_MINSUM, 3: oracle.FIXED_PHI, 4: oracle.FIXED_MINSUM8}
+    ctx = lp.Ctx(0)
+    for seed in range(60):
+        g = np.random.default_rng(20_000 + seed)
+        nreq = int(g.integers(1, 40))
+        arena_mb = int(g.choice([1, 4, 16, 64, 256]))
+        max_slots = int(g.choice([0, 1, 2, 4, 16]))
+        _say(f"case: serving sweep seed {seed}: {nreq} requests, arena {arena_mb} MiB, max_slots {max_slots}")
+        arena = torch.empty(arena_mb << 20, dtype=torch.uint8, device="cuda")
+        srv = lp.Server(ctx, arena, max_slots=max_slots, poll_us=0)
+        reqs = []
+        for _ in range(nreq):
+            fk = int(g.choice([0, 2, 3, 4]))
+            log2n = int(g.integers(1, 19))
+            n = 1 << log2n
+            mask = np.asarray(oracle.frozen_set(log2n, float(g.uniform(0.05, 0.5)), int(g.integers(0, n + 1)))[0],
+                              np.uint8)
+            fval = (g.integers(0, 2, n) & mask).astype(np.uint8)
+            if fk == 0:
+                llr = (g.standard_normal(n) * 2).astype(np.float32)
+            else:
+                lim = oracle.FIXED8_MAX if fk == 4 else oracle.FIXED_MAX
+                llr = (g.integers(-lim, lim + 1, n) if g.integers(0, 2) else g.integers(-3, 4, n)).astype(np.float32)
+            reqs.append((fk, llr, mask, fval, frame_items([(llr, mask, fval)], fk)[0]))
+        done = {}
+        for k, r in enumerate(reqs):
+            srv.submit(r[4], k)
+            if g.integers(0, 3) == 0:
+                for rid, st, lat in srv.poll():
+                    done[rid] = (st, lat)
+        _drain(srv, done)
+        srv.close()
+        torch.cuda.synchronize()
+        assert sorted(done) == list(range(nreq)), seed
+        for k, (fk, llr, mask, fval, it) in enumerate(reqs):
+            if arena_mb == 1 and it["log2n"] == 18:
+                assert done[k][0] == lp.POLAR_E_NOMEM, (seed, k)
+                continue
+            assert done[k][0] == lp.POLAR_OK, (seed, k, done[k][0])
+            u = bits_host(it["u_hat"], llr.size)
+            ref = (oracle.sc_decode(llr, mask, fval)[0] if fk == 0
+                   else oracle.sc_decode_fixed(llr.astype(np.int32), mask, fval, kinds[fk])[0])
+            assert np.array_equal(u, ref), (seed, k)
+        del arena
+    ctx.close()
